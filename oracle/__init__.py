@@ -1,0 +1,208 @@
+"""Oracle for the fast discrete linear canonical transform (arXiv:0912.1379).
+
+TEST INFRASTRUCTURE ONLY.  A plain, slow, obviously correct CPU evaluation of
+what the paper defines (FP64 in and out, long-double arithmetic inside).  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+``paper_0912_1379_amd``; neither imports the other.
+
+Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
+
+``nodes(N)``                eq. (asymcer); pinned against the true Hermite
+                            zeros' spacing and symmetry.
+``lct(f, a, b, c, d)``      Riemann sum of the LCT integral of §1 on the
+                            Algorithm's nodes (b != 0) or the b = 0 formula of
+                            §1; pinned by eq. (exa1) at the two parameter sets
+                            of §4, the Hermite-Gauss closed form, unitarity,
+                            numpy's FFT for a=d=0, b=1, the composition law
+                            and mpmath brute force.
+``lct_adjoint``             conjugate transpose of the same matrix; pinned by
+                            the inner-product identity and unitarity.
+``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d);
+                            pinned by central finite differences of ``lct``.
+``frft(f, z)``              same-grid Riemann sum of eqs. (fasy), (primcuad),
+                            (cuadtrfor); pinned by the continuum eigen-identity
+                            on Hermite functions, the z=+-i Fourier kernel of
+                            eq. (fftuno) and mpmath brute force.
+``hermite_zeros(N)``        eigenvalues of the symmetric tridiagonal H of §2;
+                            pinned by numpy hermgauss and closed-form zeros.
+``hermite_vectors``         eq. (ortvec); pinned by orthogonality, the
+                            |u_N| = 1/sqrt(N) identity and Gauss-Hermite weights.
+``Fz_exact(N, z)``          eq. (tmat); pinned by its eigen-identity and
+                            unitarity on |z| = 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liblct_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH) or (
+            os.path.getmtime(_LIBPATH) < os.path.getmtime(os.path.join(_HERE, "lct_oracle.c"))):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    i64, d = ctypes.c_int64, ctypes.c_double
+    lib.oracle_nodes.argtypes = [i64, _dp]
+    lib.oracle_lct_rows.argtypes = [i64, d, d, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_lct_rows.restype = ctypes.c_int
+    lib.oracle_lct_adjoint.argtypes = [i64, d, d, d, d, _dp, _dp]
+    lib.oracle_lct_adjoint.restype = ctypes.c_int
+    lib.oracle_lct_param_grad.argtypes = [i64, d, d, d, d, _dp, _dp, _dp]
+    lib.oracle_lct_param_grad.restype = ctypes.c_int
+    lib.oracle_frft_rows.argtypes = [i64, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_frft_rows.restype = ctypes.c_int
+    lib.oracle_hermite_zeros.argtypes = [i64, _dp]
+    lib.oracle_hermite_vectors.argtypes = [i64, _dp, _dp]
+    lib.oracle_Fz_exact.argtypes = [i64, _dp, d, d, _dp]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _cplx_in(f) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(f, dtype=np.complex128))
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def nodes(N: int) -> np.ndarray:
+    """x_k of eq. (asymcer), 0-based: (2k - N + 1) pi / (2 sqrt(2N))."""
+    x = np.empty(N, dtype=np.float64)
+    _load().oracle_nodes(N, _ptr(x))
+    return x
+
+
+def output_nodes(N: int, b: float, d: float = 1.0) -> np.ndarray:
+    """Output nodes: y_j = 4 b x_j / pi (Algorithm) for b != 0, x_j / d for b = 0."""
+    x = nodes(N)
+    if b == 0.0:
+        return x / d
+    return 4.0 * b * x / np.pi
+
+
+def lct(f, a: float, b: float, c: float, d: float, rows=None) -> np.ndarray:
+    """Discrete LCT (O1) of the length-N sample vector f (complex).
+
+    ``f`` may be 1-D (one signal) or 2-D (signals x N, all with the same M).
+    ``rows`` selects output indices (default: all N)."""
+    f = _cplx_in(f)
+    if f.ndim == 2:
+        return np.stack([lct(fi, a, b, c, d, rows) for fi in f])
+    N = f.shape[0]
+    if rows is None:
+        r = None
+        nr = N
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = r.shape[0]
+    out = np.empty(nr, dtype=np.complex128)
+    rc = _load().oracle_lct_rows(N, a, b, c, d, _ptr(f.view(np.float64)),
+                                 None if r is None else r.ctypes.data_as(_i64p), nr,
+                                 _ptr(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError(f"oracle_lct_rows failed ({rc})")
+    return out
+
+
+def lct_adjoint(g, a: float, b: float, c: float, d: float) -> np.ndarray:
+    """L^H g for the b != 0 discrete LCT matrix."""
+    g = _cplx_in(g)
+    N = g.shape[0]
+    out = np.empty(N, dtype=np.complex128)
+    rc = _load().oracle_lct_adjoint(N, a, b, c, d, _ptr(g.view(np.float64)),
+                                    _ptr(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError(f"oracle_lct_adjoint failed ({rc})")
+    return out
+
+
+def lct_param_grad(f, g, a: float, b: float, c: float, d: float) -> np.ndarray:
+    """(dl/da, dl/db, dl/dc, dl/dd) = Re sum_j conj(g_j) dG_j/dtheta."""
+    f = _cplx_in(f)
+    g = _cplx_in(g)
+    N = f.shape[0]
+    out = np.empty(4, dtype=np.float64)
+    rc = _load().oracle_lct_param_grad(N, a, b, c, d, _ptr(f.view(np.float64)),
+                                       _ptr(g.view(np.float64)), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_lct_param_grad failed ({rc})")
+    return out
+
+
+def frft(f, z: complex, rows=None) -> np.ndarray:
+    """Same-grid discrete fractional transform (O3) of f for complex |z| <= 1."""
+    f = _cplx_in(f)
+    if f.ndim == 2:
+        return np.stack([frft(fi, z, rows) for fi in f])
+    N = f.shape[0]
+    z = complex(z)
+    if rows is None:
+        r = None
+        nr = N
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = r.shape[0]
+    out = np.empty(nr, dtype=np.complex128)
+    rc = _load().oracle_frft_rows(N, z.real, z.imag, _ptr(f.view(np.float64)),
+                                  None if r is None else r.ctypes.data_as(_i64p), nr,
+                                  _ptr(out.view(np.float64)))
+    if rc == -2:
+        raise ValueError("|z| > 1")
+    if rc != 0:
+        raise ValueError(f"oracle_frft_rows failed ({rc})")
+    return out
+
+
+def hermite_zeros(N: int) -> np.ndarray:
+    """Eigenvalues of the symmetric tridiagonal H of §2 (zeros of H_N)."""
+    x = np.empty(N, dtype=np.float64)
+    _load().oracle_hermite_zeros(N, _ptr(x))
+    return x
+
+
+def hermite_vectors(N: int, x=None) -> np.ndarray:
+    """U with U[n, k] = (u_k)_n of eq. (ortvec) (0-based n, k)."""
+    if x is None:
+        x = hermite_zeros(N)
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    U = np.empty((N, N), dtype=np.float64)
+    _load().oracle_hermite_vectors(N, _ptr(x), _ptr(U))
+    return U
+
+
+def Fz_exact(N: int, z: complex, U=None) -> np.ndarray:
+    """F_z = sqrt(2 pi) U^T D(z) U of eq. (tmat)."""
+    if U is None:
+        U = hermite_vectors(N)
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
+    z = complex(z)
+    F = np.empty((N, N), dtype=np.complex128)
+    _load().oracle_Fz_exact(N, _ptr(U), z.real, z.imag, _ptr(F.view(np.float64)))
+    return F
+
+
+def lct_matrix(N: int, a: float, b: float, c: float, d: float) -> np.ndarray:
+    """Dense matrix of the discrete LCT, column k = lct(e_k)."""
+    cols = [lct(np.eye(N, dtype=np.complex128)[k], a, b, c, d) for k in range(N)]
+    return np.stack(cols, axis=1)
