@@ -1,0 +1,187 @@
+"""Benchmark of the batched discrete LCT on one MI355X.
+
+Workload (one step): 4096 signals x N = 4096 complex64 samples, one SL(2,R)
+matrix per signal (a, d ~ U(-2,2), b = +-U(0.1,2), c = (ad-1)/b), inputs
+chirped Gaussians exp(-(x-mu)^2/(2 sigma^2) + i kappa x^2) sampled on the
+nodes x_k; one step is one lct_exec_many call over the whole batch (pre-chirp,
+DFT and post-chirp in one kernel).  Inputs are resident in HBM before timing.
+
+Prints one JSON line: throughput in complex samples/s, the HBM roofline of the
+kernel (algorithmic bytes 16 B per sample over the kernel's average time from
+HIP events), the FP64 path on the same workload, the relative L2 error against
+the CPU oracle on sampled signals, and the oracle's own throughput on the
+host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "complex samples/s, FP32 batched LCT N=4096 vs FP64 path; % HBM peak; rel-L2 err"
+KERNEL_SOURCES = ["paper_0912_1379_amd/csrc/fft_core.hpp", "paper_0912_1379_amd/csrc/kernels_impl.hpp",
+                  "paper_0912_1379_amd/csrc/lct_params.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lct_fp32_n4096_b4096_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_inputs(B: int, N: int, seed_index: int = 1):
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    x_nodes, _ = lct.lct_nodes(N, 1.0)
+    g = workloads.rng(seed_index)
+    M = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    f = workloads.chirped_gaussians(x_nodes, gp)
+    return M, f
+
+
+def time_launches(fn, steps: int, warmup: int):
+    """Average duration of one call, from HIP events on the current stream."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def cpu_baseline(xh: np.ndarray, M: np.ndarray, yh: np.ndarray, budget_s: float):
+    """Oracle on a bounded sample of the same workload: whole signals (dense
+    O(N^2) Riemann sums), as many as fit the time budget (at least 2)."""
+    import oracle
+
+    N = xh.shape[1]
+    done = 0
+    errs = []
+    t0 = time.perf_counter()
+    while done < xh.shape[0] and (done < 2 or time.perf_counter() - t0 < budget_s):
+        ref = oracle.lct(xh[done].astype(np.complex128), *M[done])
+        errs.append(float(np.linalg.norm(yh[done] - ref) / np.linalg.norm(ref)))
+        done += 1
+    el = time.perf_counter() - t0
+    return {
+        "value": done * N / el,
+        "unit": "complex samples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{done} of the {xh.shape[0]} signals (N={N}, full dense Riemann sums), {el:.1f} s",
+    }, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--signals", type=int, default=4096)
+    ap.add_argument("--N", type=int, default=4096)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(signals are independent: a multi-GPU run would shard the batch with no communication)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0912_1379_amd as lct
+
+    B, N = args.signals, args.N
+    print(f"[bench] inputs: {B} signals x N={N}", file=sys.stderr, flush=True)
+    M, f = make_inputs(B, N)
+    dev = torch.device("cuda:0")
+    x32 = torch.from_numpy(f).to(dev).to(torch.complex64)
+    M4 = torch.from_numpy(M).to(dev)
+    y32 = torch.empty_like(x32)
+
+    def step32():
+        lct.lct_exec_many(x32, M4, out=y32)
+
+    ms, wall = time_launches(step32, args.steps, args.warmup)
+    samples = B * N
+    value = samples / (ms * 1e-3)
+    algo_bytes = 16.0 * samples
+    achieved_gbps = algo_bytes / (ms * 1e-3) / 1e9
+    print(f"[bench] fp32: {ms * 1e3:.1f} us/step, {achieved_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+
+    fp64 = None
+    if not args.no_fp64:
+        x64 = x32.to(torch.complex128)
+        y64 = torch.empty_like(x64)
+        ms64, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64), max(5, args.steps // 2), 3)
+        fp64 = {"ms_per_step": ms64, "value": samples / (ms64 * 1e-3),
+                "achieved_GBps": 32.0 * samples / (ms64 * 1e-3) / 1e9,
+                "fp32_speedup": ms64 / ms}
+        print(f"[bench] fp64: {ms64 * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+        del x64, y64
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("kernel_hash") == kernel_hash() and rec.get("signals") == B and rec.get("N") == N:
+            traffic = rec.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "complex samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched LCT, {B} signals x N={N} complex64, one (a,b,c,d) per signal, "
+                               "chirped-Gaussian inputs", "signals": B, "N": N, "precision": "fp32",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved_gbps / PEAK_HBM_GBPS, "traffic": traffic},
+        "wall_s_timed": wall,
+        "fp64_path": fp64,
+    }
+
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        xh = x32.cpu().numpy()
+        yh = y32.cpu().numpy().astype(np.complex128)
+        cb, errs = cpu_baseline(xh, M, yh, args.cpu_budget)
+        out["cpu_baseline"] = cb
+        out["rel_l2"] = {"max": max(errs), "median": float(np.median(errs)), "signals": len(errs)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * lct.h - C ABI of the MI355X (gfx950) fast discrete linear canonical
+ * transform of R. G. Campos and J. Figueroa, "A fast algorithm for the linear
+ * canonical transform" (arXiv:0912.1379).
+ *
+ * Notation (0-based indices j, k in [0, N)):
+ *   n_k  = 2k - N + 1
+ *   h    = pi / sqrt(2N)                                  eq. (deltk)
+ *   x_k  = h n_k / 2          input nodes                 eq. (asymcer)
+ *   y_j  = 4 b x_j / pi       output nodes (b != 0)       Algorithm, §3
+ *   y_j  = x_j / d            output nodes (b == 0)       §1 definition
+ *
+ * Data layout: complex samples interleaved {re, im}; FP32 paths use 8-byte
+ * complex64, the FP64 path 16-byte complex128.  A batch is `batch` signals of N
+ * samples stored contiguously (signal s occupies elements [s*N, (s+1)*N)).
+ * Every `in`, `out`, parameter and workspace pointer is DEVICE memory owned by
+ * the caller, unless the comment says host.  `in == out` is allowed (the
+ * transform of one signal reads all its input before writing any output).
+ *
+ * Execution is asynchronous on `stream` (a hipStream_t; NULL means the
+ * default stream).  The library never synchronises and never allocates device
+ * memory inside an exec call.  Argument errors are detected on the host before
+ * anything is enqueued and reported by the return code; nothing is written.
+ * No C++ exception crosses this interface.
+ *
+ * Supported sizes: N = 2^p 3^q 5^r with 1 <= N <= 2^24.  Sizes up to the LDS
+ * limit (FP32: 16384 points, FP64: 8192) run as one pass per signal; larger
+ * sizes use a two-pass (four-step) FFT through `out`.
+ */
+#ifndef LCT_MI355X_H
+#define LCT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum {
+    LCT_OK = 0,
+    LCT_ERR_ARG = -1,            /* null pointer, batch < 0, bad enum, misalignment */
+    LCT_ERR_NOT_UNIMODULAR = -2, /* |ad - bc - 1| > 1e-10 max(1, |ad|, |bc|) */
+    LCT_ERR_UNSUPPORTED_N = -3,  /* N not 2^p 3^q 5^r or outside [1, 2^24] */
+    LCT_ERR_DOMAIN = -4,         /* fractional order |z| > 1 */
+    LCT_ERR_WORKSPACE = -5,      /* workspace missing or too small */
+    LCT_ERR_HIP = -6,            /* a HIP runtime call failed */
+    LCT_ERR_UNSUPPORTED = -7     /* valid request this build does not run */
+};
+
+typedef enum {
+    LCT_FP32 = 0, /* complex64 data, FP32 FFT, FP64 phase reduction */
+    LCT_FP64 = 1  /* complex128 data, FP64 throughout */
+} lct_precision;
+
+typedef struct lct_plan_s *lct_plan;
+
+/*
+ * Creates an immutable plan for one size and one matrix M = (a b; c d) with
+ * ad - bc = 1 (§1).  All per-plan constants are derived here in FP64 /
+ * extended precision: the pre-chirp a x_k^2/(2b) and post-chirp d y_j^2/(2b)
+ * coefficients (Algorithm, steps 1 and 2), the index phases of eq. (dislctn)
+ * and the amplitude h (2 pi i b)^(-1/2) on the principal branch.
+ * The plan holds no device memory.  *out is set to NULL on error.
+ * c is used only when b == 0 (it is redundant otherwise).
+ */
+int lct_plan_create(lct_plan *out, int64_t N, double a, double b, double c, double d);
+int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, double d,
+                       lct_precision prec);
+void lct_plan_destroy(lct_plan p);
+
+/*
+ * Discrete LCT of `batch` signals (Algorithm, eq. algfxft1):
+ *   b != 0:  out[j] = amp * e^{i pi (N-1) j / N} e^{i d y_j^2/(2b)}
+ *                      * sum_k e^{-2 pi i j k / N} e^{i pi (N-1) k / N} e^{i a x_k^2/(2b)} in[k],
+ *            amp = h (2 pi i b)^(-1/2) e^{-i pi (N-1)^2/(2N)},
+ *            which equals the Riemann sum of the integral of §1 at y_j;
+ *            out[j] approximates G(4 b x_j / pi).
+ *   b == 0:  out[j] = sqrt(d) e^{i c x_j^2/(2d)} in[j]   (§1, f(d y_j) = f(x_j)).
+ * The DFT sign is the one of the integral (exp(-i x y / b)); the Algorithm box
+ * prints the opposite sign, which returns G at -y_j.
+ */
+int lct_exec(lct_plan p, const void *in, void *out, int64_t batch, hipStream_t stream);
+
+/*
+ * Same transform with one matrix per signal: M4 is DEVICE memory holding
+ * batch x 4 doubles (a, b, c, d) in that order.  M4 is not validated on the
+ * host (it lives on the device); rows with b == 0 take the diagonal path.
+ * This extends the paper's single-matrix statement to a batch.
+ */
+int lct_exec_many(int64_t N, lct_precision prec, const double *M4, const void *in, void *out,
+                  int64_t batch, hipStream_t stream);
+
+/*
+ * Adjoint (conjugate transpose) of the b != 0 transform:
+ *   out = L^H g,  L^H = (pi / (4|b|)) L^{-1}   (the matrix is unitary up to
+ * sqrt(4|b|/pi), §5).  This is the input gradient of a real loss in the
+ * complex-gradient convention grad_in = L^H grad_out.
+ * Returns LCT_ERR_UNSUPPORTED for plans with b == 0.
+ */
+int lct_exec_adjoint(lct_plan p, const void *g, void *out, int64_t batch, hipStream_t stream);
+int lct_exec_many_adjoint(int64_t N, lct_precision prec, const double *M4, const void *g,
+                          void *out, int64_t batch, hipStream_t stream);
+
+/*
+ * Parameter gradient of a real loss l for the b != 0 transform, per signal:
+ *   grad4[s] = (dl/da, dl/db, dl/dc, dl/dd),  dl/dtheta = Re sum_j conj(g_j) dG_j/dtheta,
+ * g = dl/dRe G + i dl/dIm G (DEVICE, batch x N complex), f the forward input,
+ * with the output nodes y_j moving with b.  dl/dc = 0 since c does not enter
+ * for b != 0.  grad4 is DEVICE memory of batch x 4 doubles.
+ */
+int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const void *f,
+                        const void *g, double *grad4, int64_t batch, hipStream_t stream);
+
+/*
+ * Same-grid discrete fractional Fourier transform of eqs. (fasy), (primcuad),
+ * (cuadtrfor), y_j = x_j, for complex order |z| <= 1:
+ *   out[j] = sum_k h sqrt(2/(1-z^2)) exp(-[(1+z^2)(x_j^2+x_k^2) - 4 z x_j x_k]/(2(1-z^2))) in[k].
+ * Evaluated as Gaussian-chirp diagonal * FFT convolution * diagonal with every
+ * factor of modulus <= 1.  z = 1 and z = -1 return the continuum limits
+ * sqrt(2 pi) in[j] and sqrt(2 pi) in[N-1-j].  |z| > 1 (beyond 1e-12) gives
+ * LCT_ERR_DOMAIN.  Only N and the precision of the plan are used.
+ */
+int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,
+              hipStream_t stream);
+/* One order per signal: Z2 is DEVICE memory of batch x 2 doubles (re, im). */
+int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out,
+                   int64_t batch, hipStream_t stream);
+
+/*
+ * Host helper: input nodes x (N doubles, eq. asymcer) and output nodes y
+ * (N doubles: 4 b x_j / pi, or x_j / d when b == 0).  Either pointer may be NULL.
+ * Host memory.  Returns LCT_ERR_ARG for N < 1 or b == d == 0.
+ */
+int lct_nodes(int64_t N, double b, double d, double *x, double *y);
+
+/* Static description of a return code. */
+const char *lct_strerror(int code);
+
+/* Largest N that runs as a single pass for the precision (host query). */
+int64_t lct_max_single_pass(lct_precision prec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCT_MI355X_H */

@@ -1,0 +1,299 @@
+"""MI355X (gfx950) fast discrete linear canonical transform.
+
+Implements the scaling-chirp-DFT-chirp-scaling factorisation of R. G. Campos
+and J. Figueroa, "A fast algorithm for the linear canonical transform"
+(arXiv:0912.1379): the Algorithm of §3 (eq. algfxft1) for batches of signals
+with one or many matrices M = (a b; c d), ad - bc = 1, and the same-grid
+fractional Fourier transform of §2 (eqs. fasy, primcuad, cuadtrfor) for complex
+orders |z| <= 1.  All arithmetic runs in the HIP library behind the C ABI of
+``include/lct.h``; this package marshals torch tensors (device memory and the
+current stream) into those calls.
+
+The functions named like the C entry points take and return torch tensors:
+
+    plan = lct_plan_create(N, a, b, c, d, precision=LCT_FP32)
+    y = lct_exec(plan, x)                 # x: (..., N) complex64 / complex128 on cuda
+    y = lct_exec_many(x, M4)              # M4: (batch, 4) float64 on cuda
+    g = lct_exec_adjoint(plan, y)         # L^H y
+    g = lct_exec_many_adjoint(y, M4)
+    d = lct_param_grad_many(x, gy, M4)    # (batch, 4) float64: dl/d(a, b, c, d)
+    y = frft_exec(plan, z, x)             # same-grid fractional transform
+    y = frft_exec_many(x, Z2)             # Z2: (batch, 2) float64 (re z, im z)
+    x, y = lct_nodes(N, b, d)             # input / output nodes (numpy)
+
+``lct(x, M)`` and ``frft(x, z)`` are conveniences; ``LCTFunction`` is the
+autograd function whose backward is the adjoint transform plus the
+parameter-gradient kernel.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODULAR,  # noqa: F401
+                   LCT_ERR_UNSUPPORTED, LCT_ERR_UNSUPPORTED_N, LCT_ERR_WORKSPACE, LCT_FP32, LCT_FP64,
+                   LCT_OK, LctError)
+
+__all__ = [
+    "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
+    "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
+    "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
+    "LCT_FP32", "LCT_FP64",
+]
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _prec_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return LCT_FP32
+    if t.dtype == torch.complex128:
+        return LCT_FP64
+    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+
+
+def _dtype_of(prec: int) -> torch.dtype:
+    return torch.complex128 if prec == LCT_FP64 else torch.complex64
+
+
+def _check_data(t: torch.Tensor, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU (the library has no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _batch_of(t: torch.Tensor, N: int) -> int:
+    if t.dim() == 0 or t.shape[-1] != N:
+        raise ValueError(f"last dimension must be N = {N}, got shape {tuple(t.shape)}")
+    return t.numel() // N
+
+
+def _out_like(x: torch.Tensor, out):
+    if out is None:
+        return torch.empty_like(x)
+    _check_data(out, "out")
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError("out must match the input's shape, dtype and device")
+    return out
+
+
+class Plan:
+    """Owns an ``lct_plan`` handle (one size, one matrix, one precision)."""
+
+    def __init__(self, N: int, a: float, b: float, c: float, d: float, precision: int = LCT_FP32):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.lct_plan_create_ex(ctypes.byref(h), int(N), float(a), float(b), float(c), float(d),
+                                          int(precision)), "lct_plan_create_ex")
+        self._h = h
+        self.N = int(N)
+        self.M = (float(a), float(b), float(c), float(d))
+        self.precision = int(precision)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().lct_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def lct_plan_create(N, a, b, c, d, precision: int = LCT_FP32) -> Plan:
+    return Plan(N, a, b, c, d, precision)
+
+
+lct_plan_create_ex = lct_plan_create
+
+
+def lct_plan_destroy(plan: Plan) -> None:
+    plan.destroy()
+
+
+def _plan_io(plan: Plan, x: torch.Tensor, out):
+    _check_data(x, "x")
+    if _prec_of(x) != plan.precision:
+        raise TypeError("input dtype does not match the plan's precision")
+    batch = _batch_of(x, plan.N)
+    return batch, _out_like(x, out)
+
+
+def lct_exec(plan: Plan, x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    batch, out = _plan_io(plan, x, out)
+    rc = _lib.load().lct_exec(plan.handle, x.data_ptr(), out.data_ptr(), batch, _stream_handle(stream))
+    _lib.check(rc, "lct_exec")
+    return out
+
+
+def lct_exec_adjoint(plan: Plan, g: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    batch, out = _plan_io(plan, g, out)
+    rc = _lib.load().lct_exec_adjoint(plan.handle, g.data_ptr(), out.data_ptr(), batch, _stream_handle(stream))
+    _lib.check(rc, "lct_exec_adjoint")
+    return out
+
+
+def _check_params(P: torch.Tensor, batch: int, width: int, name: str) -> None:
+    _check_data(P, name)
+    if P.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if P.numel() != batch * width:
+        raise ValueError(f"{name} must hold {batch} x {width} values")
+
+
+def lct_exec_many(x: torch.Tensor, M4: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    _check_data(x, "x")
+    prec = _prec_of(x)
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    _check_params(M4, batch, 4, "M4")
+    out = _out_like(x, out)
+    rc = _lib.load().lct_exec_many(N, prec, M4.data_ptr(), x.data_ptr(), out.data_ptr(), batch,
+                                   _stream_handle(stream))
+    _lib.check(rc, "lct_exec_many")
+    return out
+
+
+def lct_exec_many_adjoint(g: torch.Tensor, M4: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    _check_data(g, "g")
+    prec = _prec_of(g)
+    N = g.shape[-1]
+    batch = _batch_of(g, N)
+    _check_params(M4, batch, 4, "M4")
+    out = _out_like(g, out)
+    rc = _lib.load().lct_exec_many_adjoint(N, prec, M4.data_ptr(), g.data_ptr(), out.data_ptr(), batch,
+                                           _stream_handle(stream))
+    _lib.check(rc, "lct_exec_many_adjoint")
+    return out
+
+
+def lct_param_grad_many(f: torch.Tensor, g: torch.Tensor, M4: torch.Tensor, grad4=None,
+                        stream=None) -> torch.Tensor:
+    _check_data(f, "f")
+    _check_data(g, "g")
+    prec = _prec_of(f)
+    if g.dtype != f.dtype or g.shape != f.shape:
+        raise ValueError("f and g must have the same shape and dtype")
+    N = f.shape[-1]
+    batch = _batch_of(f, N)
+    _check_params(M4, batch, 4, "M4")
+    if grad4 is None:
+        grad4 = torch.empty((batch, 4), dtype=torch.float64, device=f.device)
+    else:
+        _check_params(grad4, batch, 4, "grad4")
+    rc = _lib.load().lct_param_grad_many(N, prec, M4.data_ptr(), f.data_ptr(), g.data_ptr(), grad4.data_ptr(),
+                                         batch, _stream_handle(stream))
+    _lib.check(rc, "lct_param_grad_many")
+    return grad4
+
+
+def frft_exec(plan: Plan, z: complex, x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    batch, out = _plan_io(plan, x, out)
+    z = complex(z)
+    rc = _lib.load().frft_exec(plan.handle, z.real, z.imag, x.data_ptr(), out.data_ptr(), batch,
+                               _stream_handle(stream))
+    _lib.check(rc, "frft_exec")
+    return out
+
+
+def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    _check_data(x, "x")
+    prec = _prec_of(x)
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    _check_params(Z2, batch, 2, "Z2")
+    out = _out_like(x, out)
+    rc = _lib.load().frft_exec_many(N, prec, Z2.data_ptr(), x.data_ptr(), out.data_ptr(), batch,
+                                    _stream_handle(stream))
+    _lib.check(rc, "frft_exec_many")
+    return out
+
+
+def lct_nodes(N: int, b: float, d: float = 1.0):
+    """Input nodes x_k (eq. asymcer) and output nodes y_j (numpy float64)."""
+    x = np.empty(N, dtype=np.float64)
+    y = np.empty(N, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _lib.load().lct_nodes(int(N), float(b), float(d), x.ctypes.data_as(dp), y.ctypes.data_as(dp))
+    _lib.check(rc, "lct_nodes")
+    return x, y
+
+
+def lct_strerror(code: int) -> str:
+    return _lib.load().lct_strerror(int(code)).decode()
+
+
+def lct_max_single_pass(precision: int = LCT_FP32) -> int:
+    return int(_lib.load().lct_max_single_pass(int(precision)))
+
+
+def _as_M4(M, batch: int, device) -> torch.Tensor:
+    if isinstance(M, torch.Tensor):
+        M4 = M.to(device=device, dtype=torch.float64)
+    else:
+        M4 = torch.as_tensor(np.asarray(M, dtype=np.float64), device=device)
+    if M4.dim() == 1:
+        M4 = M4.reshape(1, 4).expand(batch, 4)
+    return M4.reshape(batch, 4).contiguous()
+
+
+class LCTFunction(torch.autograd.Function):
+    """y = L_M f per signal; backward gives L^H grad_y and dl/d(a, b, c, d)."""
+
+    @staticmethod
+    def forward(ctx, f: torch.Tensor, M4: torch.Tensor):
+        f = f.contiguous()
+        M4 = M4.contiguous()
+        y = lct_exec_many(f, M4)
+        ctx.save_for_backward(f, M4)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy: torch.Tensor):
+        f, M4 = ctx.saved_tensors
+        gy = gy.contiguous()
+        gf = lct_exec_many_adjoint(gy, M4) if ctx.needs_input_grad[0] else None
+        gM = lct_param_grad_many(f, gy, M4).reshape(M4.shape) if ctx.needs_input_grad[1] else None
+        return gf, gM
+
+
+def lct(x: torch.Tensor, M) -> torch.Tensor:
+    """Discrete LCT of every length-N signal of x (last dimension) for one matrix
+    M = (a, b, c, d) or one matrix per signal (a (batch, 4) float64 tensor)."""
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    M4 = _as_M4(M, batch, x.device)
+    return LCTFunction.apply(x, M4)
+
+
+def frft(x: torch.Tensor, z) -> torch.Tensor:
+    """Same-grid discrete fractional transform of every signal of x for one
+    complex order z or one order per signal (a (batch,) complex tensor)."""
+    _check_data(x, "x")
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    if isinstance(z, torch.Tensor):
+        zc = z.to(torch.complex128).reshape(batch)
+        Z2 = torch.view_as_real(zc).to(device=x.device).contiguous()
+    else:
+        z = complex(z)
+        Z2 = torch.tensor([[z.real, z.imag]], dtype=torch.float64, device=x.device).expand(batch, 2).contiguous()
+    return frft_exec_many(x, Z2)

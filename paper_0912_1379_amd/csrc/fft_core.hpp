@@ -1,0 +1,447 @@
+// fft_core.hpp - device building blocks of the discrete LCT on gfx950:
+// complex arithmetic, phase evaluation from turns reduced in FP64, small DFT
+// butterflies, and a register-staged Stockham FFT held in LDS.
+//
+// The transform of the paper (Algorithm, eq. algfxft1) is a diagonal
+// ("chirp-scaling") times a length-N DFT times a diagonal.  The DFT is
+// computed here as a Stockham autosort FFT: each thread of a signal owns the E
+// elements at positions t + T e (T = N / E threads per signal, e in [0, E)).
+// Every stage reads exactly those positions, applies E / R radix-R butterflies
+// in registers, and writes its outputs to the Stockham positions in LDS; the
+// last stage's outputs land again on positions t + T e, so the first stage
+// can read from HBM and the last stage can write to HBM directly, both
+// coalesced across threads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lctk {
+
+template <typename R> struct C {
+    R x, y;
+};
+
+template <typename R> __device__ __forceinline__ C<R> cadd(C<R> a, C<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ __forceinline__ C<R> csub(C<R> a, C<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __device__ __forceinline__ C<R> cmul(C<R> a, C<R> b)
+{
+    return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+template <typename R> __device__ __forceinline__ C<R> cconj(C<R> a) { return {a.x, -a.y}; }
+template <typename R> __device__ __forceinline__ C<R> cscale(C<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by -i
+template <typename R> __device__ __forceinline__ C<R> cmul_mi(C<R> a) { return {a.y, -a.x}; }
+// multiply by +i
+template <typename R> __device__ __forceinline__ C<R> cmul_pi(C<R> a) { return {-a.y, a.x}; }
+
+// memory vector types: 8-byte complex64 / 16-byte complex128
+template <typename R> struct Vec;
+template <> struct Vec<float> { using T = float2; };
+template <> struct Vec<double> { using T = double2; };
+
+template <typename R> __device__ __forceinline__ C<R> ldc(const typename Vec<R>::T *p)
+{
+    typename Vec<R>::T v = *p;
+    return {v.x, v.y};
+}
+template <typename R> __device__ __forceinline__ void stc(typename Vec<R>::T *p, C<R> a)
+{
+    typename Vec<R>::T v;
+    v.x = a.x;
+    v.y = a.y;
+    *p = v;
+}
+
+// ---------------------------------------------------------------------------
+// Phases.  A phase is carried in turns (1 turn = 2 pi rad), reduced to
+// [-1/2, 1/2] in FP64, then evaluated as cos/sin(2 pi t) in the data precision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ C<float> cis_turns(float t)
+{
+    float s, c;
+    sincospif(2.0f * t, &s, &c);
+    return {c, s};
+}
+__device__ __forceinline__ C<double> cis_turns(double t)
+{
+    double s, c;
+    sincospi(2.0 * t, &s, &c);
+    return {c, s};
+}
+template <typename R> __device__ __forceinline__ C<R> cis_turns_from(double t);
+template <> __device__ __forceinline__ C<float> cis_turns_from<float>(double t) { return cis_turns((float)t); }
+template <> __device__ __forceinline__ C<double> cis_turns_from<double>(double t) { return cis_turns(t); }
+
+__device__ __forceinline__ double frac_turns(double t) { return t - rint(t); }
+
+// Coefficient of a quadratic phase in turns, kept as an unevaluated sum
+// hi + lo of two doubles (lo = 0 for the FP32 path, where one double suffices).
+struct Quad {
+    double hi, lo;
+};
+
+// frac(q * m2) for an exact integer m2 < 2^53 held in a double.
+// Contraction must stay off here: fusing the product into the subtraction
+// below would count its rounding error twice.
+__device__ __forceinline__ double quad_turns(Quad q, double m2)
+{
+#pragma clang fp contract(off)
+    double p = q.hi * m2;
+    double e = fma(q.hi, m2, -p); // exact rounding error of the product
+    double t = p - rint(p);
+    return t + fma(q.lo, m2, e);
+}
+
+// Index phase of eq. (dislctn) with the integral's sign: (N-1) i / (2N) turns,
+// reduced exactly: (N-1) i = N i - i and N i = N (i mod 2) (mod 2N).
+__device__ __forceinline__ double index_turns(int i, int N, double inv2N)
+{
+    int r = (i & 1) ? (N - i) : (-i);
+    return (double)r * inv2N;
+}
+
+// ---------------------------------------------------------------------------
+// Small forward DFTs U_s = sum_r u_r exp(-2 pi i r s / R), in place.
+// ---------------------------------------------------------------------------
+template <typename R> struct K {
+    static constexpr R SQH = (R)0.70710678118654752440084436210484904;  // sqrt(1/2)
+    static constexpr R C8 = (R)0.92387953251128675612818318939678829;   // cos(pi/8)
+    static constexpr R S8 = (R)0.38268343236508977172845998403039887;   // sin(pi/8)
+    static constexpr R S3 = (R)0.86602540378443864676372317075293618;   // sin(pi/3)
+    static constexpr R C5A = (R)0.30901699437494742410229341718281906;  // cos(2pi/5)
+    static constexpr R C5B = (R)-0.80901699437494742410229341718281906; // cos(4pi/5)
+    static constexpr R S5A = (R)0.95105651629515357211643933337938214;  // sin(2pi/5)
+    static constexpr R S5B = (R)0.58778525229247312916870595463907277;  // sin(4pi/5)
+};
+
+template <typename R> __device__ __forceinline__ void dft2(C<R> &a, C<R> &b)
+{
+    C<R> t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <typename R> __device__ __forceinline__ void dft3(C<R> &a, C<R> &b, C<R> &c)
+{
+    C<R> s = cadd(b, c);
+    C<R> d = csub(b, c);
+    C<R> m = {a.x - (R)0.5 * s.x, a.y - (R)0.5 * s.y};
+    C<R> r = cscale(cmul_mi(d), K<R>::S3); // -i sin(pi/3) (b - c)
+    a = cadd(a, s);
+    b = cadd(m, r);
+    c = csub(m, r);
+}
+
+template <typename R> __device__ __forceinline__ void dft4(C<R> &a, C<R> &b, C<R> &c, C<R> &d)
+{
+    C<R> s0 = cadd(a, c), d0 = csub(a, c);
+    C<R> s1 = cadd(b, d), d1 = cmul_mi(csub(b, d));
+    a = cadd(s0, s1);
+    c = csub(s0, s1);
+    b = cadd(d0, d1);
+    d = csub(d0, d1);
+}
+
+template <typename R> __device__ __forceinline__ void dft5(C<R> &u0, C<R> &u1, C<R> &u2, C<R> &u3, C<R> &u4)
+{
+    C<R> b1 = cadd(u1, u4), d1 = csub(u1, u4);
+    C<R> b2 = cadd(u2, u3), d2 = csub(u2, u3);
+    C<R> m1 = {u0.x + K<R>::C5A * b1.x + K<R>::C5B * b2.x, u0.y + K<R>::C5A * b1.y + K<R>::C5B * b2.y};
+    C<R> m2 = {u0.x + K<R>::C5B * b1.x + K<R>::C5A * b2.x, u0.y + K<R>::C5B * b1.y + K<R>::C5A * b2.y};
+    C<R> r1 = {K<R>::S5A * d1.x + K<R>::S5B * d2.x, K<R>::S5A * d1.y + K<R>::S5B * d2.y};
+    C<R> r2 = {K<R>::S5B * d1.x - K<R>::S5A * d2.x, K<R>::S5B * d1.y - K<R>::S5A * d2.y};
+    u0 = cadd(u0, cadd(b1, b2));
+    C<R> i1 = cmul_mi(r1), i2 = cmul_mi(r2);
+    u1 = cadd(m1, i1);
+    u4 = csub(m1, i1);
+    u2 = cadd(m2, i2);
+    u3 = csub(m2, i2);
+}
+
+// radix 8 = 2 x 4
+template <typename R> __device__ __forceinline__ void dft8(C<R> *u)
+{
+    dft4(u[0], u[2], u[4], u[6]);
+    dft4(u[1], u[3], u[5], u[7]);
+    // twiddles W8^p on the odd sub-transform
+    u[3] = cmul(u[3], C<R>{K<R>::SQH, -K<R>::SQH});
+    u[5] = cmul_mi(u[5]);
+    u[7] = cmul(u[7], C<R>{-K<R>::SQH, -K<R>::SQH});
+    C<R> o[8];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        C<R> e = u[2 * p], od = u[2 * p + 1];
+        o[p] = cadd(e, od);
+        o[p + 4] = csub(e, od);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        u[s] = o[s];
+}
+
+// radix 16 = 4 x 4
+template <typename R> __device__ __forceinline__ void dft16(C<R> *u)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        dft4(u[q], u[q + 4], u[q + 8], u[q + 12]);
+    // A_q[p] sits in u[q + 4p]; twiddle W16^(q p)
+    const C<R> w1 = {K<R>::C8, -K<R>::S8}, w2 = {K<R>::SQH, -K<R>::SQH}, w3 = {K<R>::S8, -K<R>::C8};
+    const C<R> w6 = {-K<R>::SQH, -K<R>::SQH}, w9 = {-K<R>::C8, K<R>::S8};
+    u[1 + 4] = cmul(u[1 + 4], w1);
+    u[1 + 8] = cmul(u[1 + 8], w2);
+    u[1 + 12] = cmul(u[1 + 12], w3);
+    u[2 + 4] = cmul(u[2 + 4], w2);
+    u[2 + 8] = cmul_mi(u[2 + 8]);
+    u[2 + 12] = cmul(u[2 + 12], w6);
+    u[3 + 4] = cmul(u[3 + 4], w3);
+    u[3 + 8] = cmul(u[3 + 8], w6);
+    u[3 + 12] = cmul(u[3 + 12], w9);
+    C<R> o[16];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        C<R> a = u[0 + 4 * p], b = u[1 + 4 * p], c = u[2 + 4 * p], d = u[3 + 4 * p];
+        dft4(a, b, c, d);
+        o[p] = a;
+        o[p + 4] = b;
+        o[p + 8] = c;
+        o[p + 12] = d;
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        u[s] = o[s];
+}
+
+template <int RAD, typename R> __device__ __forceinline__ void dft(C<R> *u)
+{
+    if constexpr (RAD == 2) {
+        dft2(u[0], u[1]);
+    } else if constexpr (RAD == 3) {
+        dft3(u[0], u[1], u[2]);
+    } else if constexpr (RAD == 4) {
+        dft4(u[0], u[1], u[2], u[3]);
+    } else if constexpr (RAD == 5) {
+        dft5(u[0], u[1], u[2], u[3], u[4]);
+    } else if constexpr (RAD == 8) {
+        dft8(u);
+    } else if constexpr (RAD == 16) {
+        dft16(u);
+    }
+}
+
+// Twiddle powers w^r, r = 1..RAD-1, from w = w^1, with product depth <= 4.
+template <int RAD, typename R> __device__ __forceinline__ void twiddle_powers(C<R> w1, C<R> *w)
+{
+    w[1] = w1;
+    if constexpr (RAD > 2) w[2] = cmul(w1, w1);
+    if constexpr (RAD > 3) w[3] = cmul(w[2], w1);
+    if constexpr (RAD > 4) w[4] = cmul(w[2], w[2]);
+    if constexpr (RAD > 5) {
+#pragma unroll
+        for (int r = 5; r < RAD && r < 8; ++r)
+            w[r] = cmul(w[4], w[r - 4]);
+    }
+    if constexpr (RAD > 8) {
+        w[8] = cmul(w[4], w[4]);
+#pragma unroll
+        for (int r = 9; r < RAD; ++r)
+            w[r] = cmul(w[8], w[r - 8]);
+    }
+}
+
+// LDS index with one pad element every 16 (breaks power-of-two bank strides).
+__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
+__host__ __device__ constexpr int lds_elems(int N) { return N + (N >> 4) + 1; }
+
+// One Stockham stage of radix RAD on the E register values of thread t.
+// Input slot i + Q r (Q = E / RAD) holds position t + T (i + Q r); butterfly
+// i has index b = t + T i and twiddle W_{Ns RAD}^{(b mod Ns) r}.  Outputs are
+// left in place: slot i + Q s holds output s of butterfly i.
+template <int E, int RAD, typename R>
+__device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
+{
+    constexpr int Q = E / RAD;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        C<R> u[RAD];
+#pragma unroll
+        for (int r = 0; r < RAD; ++r)
+            u[r] = v[i + Q * r];
+        if (Ns > 1) {
+            int b = t + T * i;
+            int j = b % Ns;
+            // base angle -j / (Ns RAD) turns
+            double tb = -(double)j / (double)(Ns * RAD);
+            C<R> w[RAD];
+            twiddle_powers<RAD>(cis_turns_from<R>(tb), w);
+#pragma unroll
+            for (int r = 1; r < RAD; ++r)
+                u[r] = cmul(u[r], w[r]);
+        }
+        dft<RAD>(u);
+#pragma unroll
+        for (int s = 0; s < RAD; ++s)
+            v[i + Q * s] = u[s];
+    }
+}
+
+// Writes the outputs of a stage to their Stockham positions in LDS.
+template <int E, int RAD, typename R>
+__device__ __forceinline__ void stage_write(C<R> *lds, const C<R> *v, int t, int T, int Ns)
+{
+    constexpr int Q = E / RAD;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int b = t + T * i;
+        int j = b % Ns;
+        int base = (b - j) * RAD + j;
+#pragma unroll
+        for (int s = 0; s < RAD; ++s)
+            lds[lds_pad(base + s * Ns)] = v[i + Q * s];
+    }
+}
+
+template <int E, typename R>
+__device__ __forceinline__ void stage_read(const C<R> *lds, C<R> *v, int t, int T)
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = lds[lds_pad(t + T * e)];
+}
+
+template <int E, typename R>
+__device__ __forceinline__ void run_stage(int rad, C<R> *v, int t, int T, int Ns)
+{
+    switch (rad) {
+    case 16:
+        if constexpr (E % 16 == 0) stage_compute<E, 16>(v, t, T, Ns);
+        break;
+    case 8:
+        if constexpr (E % 8 == 0) stage_compute<E, 8>(v, t, T, Ns);
+        break;
+    case 5:
+        if constexpr (E % 5 == 0) stage_compute<E, 5>(v, t, T, Ns);
+        break;
+    case 4:
+        if constexpr (E % 4 == 0) stage_compute<E, 4>(v, t, T, Ns);
+        break;
+    case 3:
+        if constexpr (E % 3 == 0) stage_compute<E, 3>(v, t, T, Ns);
+        break;
+    case 2:
+        if constexpr (E % 2 == 0) stage_compute<E, 2>(v, t, T, Ns);
+        break;
+    default:
+        break;
+    }
+}
+
+template <int E, typename R>
+__device__ __forceinline__ void run_write(int rad, C<R> *lds, const C<R> *v, int t, int T, int Ns)
+{
+    switch (rad) {
+    case 16:
+        if constexpr (E % 16 == 0) stage_write<E, 16>(lds, v, t, T, Ns);
+        break;
+    case 8:
+        if constexpr (E % 8 == 0) stage_write<E, 8>(lds, v, t, T, Ns);
+        break;
+    case 5:
+        if constexpr (E % 5 == 0) stage_write<E, 5>(lds, v, t, T, Ns);
+        break;
+    case 4:
+        if constexpr (E % 4 == 0) stage_write<E, 4>(lds, v, t, T, Ns);
+        break;
+    case 3:
+        if constexpr (E % 3 == 0) stage_write<E, 3>(lds, v, t, T, Ns);
+        break;
+    case 2:
+        if constexpr (E % 2 == 0) stage_write<E, 2>(lds, v, t, T, Ns);
+        break;
+    default:
+        break;
+    }
+}
+
+// Radix schedule passed by value to kernels (stages in execution order).
+// Kernels read it in place from their argument block (never copy it into a
+// private array, which would live in scratch memory).
+struct Sched {
+    int nst;
+    int rad[24];
+};
+
+// Radix of stage s of a compile-time schedule: greedy largest radix that
+// divides both E and the remaining length.
+__host__ __device__ constexpr int fixed_radix(int N, int E, int s)
+{
+    const int cand[6] = {16, 8, 5, 4, 3, 2};
+    int rem = N;
+    int r = 1;
+    for (int k = 0; k <= s; ++k) {
+        r = 1;
+        for (int c = 0; c < 6; ++c) {
+            if (E % cand[c] == 0 && rem % cand[c] == 0) {
+                r = cand[c];
+                break;
+            }
+        }
+        rem /= r;
+    }
+    return r;
+}
+__host__ __device__ constexpr int fixed_nstages(int N, int E)
+{
+    int s = 0;
+    while (s < 32 && fixed_radix(N, E, s) > 1)
+        ++s;
+    return s;
+}
+
+// In-LDS forward FFT of the register values v (positions t + T e), in place.
+// All threads of the work-group must call it (it contains barriers).  On
+// return v[e] holds output position t + T e.  The LDS buffer is free again
+// after the first barrier of the next call.
+// Compile-time schedule version: every stage's radix and stride are constants.
+template <int E, int N, int S, int NS, typename R>
+__device__ __forceinline__ void fft_lds_fixed_from(C<R> *v, C<R> *lds, int t)
+{
+    constexpr int NST = fixed_nstages(N, E);
+    if constexpr (S < NST) {
+        constexpr int RAD = fixed_radix(N, E, S);
+        constexpr int T = N / E;
+        stage_compute<E, RAD>(v, t, T, NS);
+        if constexpr (S + 1 < NST) {
+            __syncthreads();
+            stage_write<E, RAD>(lds, v, t, T, NS);
+            __syncthreads();
+            stage_read<E>(lds, v, t, T);
+        }
+        fft_lds_fixed_from<E, N, S + 1, NS * RAD>(v, lds, t);
+    }
+}
+template <int E, int N, typename R>
+__device__ __forceinline__ void fft_lds_fixed(C<R> *v, C<R> *lds, int t)
+{
+    fft_lds_fixed_from<E, N, 0, 1>(v, lds, t);
+}
+
+template <int E, typename R>
+__device__ __forceinline__ void fft_lds(C<R> *v, C<R> *lds, int t, int T, const Sched &sc)
+{
+    int Ns = 1;
+    for (int s = 0; s < sc.nst; ++s) {
+        const int rad = sc.rad[s];
+        run_stage<E>(rad, v, t, T, Ns);
+        if (s + 1 < sc.nst) {
+            __syncthreads(); // previous readers of lds are done
+            run_write<E>(rad, lds, v, t, T, Ns);
+            __syncthreads();
+            stage_read<E>(lds, v, t, T);
+        }
+        Ns *= rad;
+    }
+}
+
+} // namespace lctk

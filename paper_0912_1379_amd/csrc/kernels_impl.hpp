@@ -1,0 +1,396 @@
+// kernels_impl.hpp - single-pass (in-LDS) kernels of the discrete LCT and of
+// the same-grid fractional transform for gfx950.
+//
+// One work-group holds S signals of N points; each signal is processed by
+// T = N / E threads that own E complex values each (see fft_core.hpp).  The
+// chirp-scaling diagonals of the Algorithm (steps 1 and 2) are applied while
+// the samples travel between HBM and registers, so HBM sees exactly one read
+// and one write per sample.
+#pragma once
+#include "lct_kernels.hpp"
+
+#include "fft_core.hpp"
+#include "lct_params.hpp"
+
+namespace lctk {
+
+enum Mode { MODE_FWD = 0, MODE_ADJ = 1 };
+
+// n^2 for n = 2i - N + 1, exact in double for N < 2^26.
+__device__ __forceinline__ double nsq(int i, int N)
+{
+    double n = (double)(2 * i - N + 1);
+    return n * n;
+}
+
+template <typename R>
+__device__ __forceinline__ C<R> pre_factor(const LctConst &k, int i, int N, double inv2N)
+{
+    double t = quad_turns(Quad{k.pre_hi, k.pre_lo}, nsq(i, N)) + index_turns(i, N, inv2N);
+    return cis_turns_from<R>(frac_turns(t));
+}
+
+template <typename R>
+__device__ __forceinline__ C<R> post_factor(const LctConst &k, int j, int N, double inv2N)
+{
+    double t = quad_turns(Quad{k.post_hi, k.post_lo}, nsq(j, N)) + index_turns(j, N, inv2N);
+    C<R> c = cis_turns_from<R>(frac_turns(t));
+    return cmul(c, C<R>{(R)k.amp_re, (R)k.amp_im});
+}
+
+// Quadratic phase of the positions i_e = t + T e a thread owns, as a
+// polynomial in e:  q n_e^2 (+ (N-1) i_e / (2N))  =  A + e B + e^2 C  (turns),
+// n_e = n_t + 2 T e.  A, B, C are reduced modulo 1 once per thread from exact
+// integers, so each element costs two FMAs and one reduction.
+struct ThreadChirp {
+    double A, B, C;
+};
+
+__device__ __forceinline__ ThreadChirp thread_chirp(double qhi, double qlo, bool with_index, int t, int T, int N,
+                                                    double inv2N)
+{
+    const Quad q{qhi, qlo};
+    const double nt = (double)(2 * t - N + 1);
+    double A = quad_turns(q, nt * nt);
+    double B = quad_turns(q, 4.0 * (double)T * nt);
+    double C = quad_turns(q, 4.0 * (double)T * (double)T);
+    if (with_index) {
+        A += index_turns(t, N, inv2N);
+        B += index_turns(T, N, inv2N);
+    }
+    return {frac_turns(A), frac_turns(B), frac_turns(C)};
+}
+
+template <typename R>
+__device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
+{
+    const double fe = (double)e;
+    double u = fma(c.B, fe, fma(c.C, fe * fe, c.A));
+    return cis_turns_from<R>(frac_turns(u));
+}
+
+// ---------------------------------------------------------------------------
+// LCT forward (MODE_FWD) / adjoint (MODE_ADJ).  Per-signal constants come from
+// args.k (one matrix for the batch) or are derived from M4[sig].
+//   forward: load f, times pre-chirp; DFT; times post-chirp and amplitude.
+//   adjoint: L^H g = conj(pre (DFT(post conj(g)))) (the DFT matrix is symmetric).
+// ---------------------------------------------------------------------------
+template <typename R, int E, int NFIX, int MODE>
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
+    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, LctArgs args)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+
+    const int N = NFIX > 0 ? NFIX : args.N;
+    const int T = NFIX > 0 ? NFIX / E : args.T;
+
+    const int sl = (int)threadIdx.x / T; // signal slot within the work-group
+    const int t = (int)threadIdx.x - sl * T;
+    const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
+    const bool live = sig < args.batch;
+    C<R> *lds = smem + (size_t)sl * lds_elems(N);
+    const double inv2N = 0.5 / (double)N;
+
+    LctConst k;
+    if (args.M4 != nullptr) {
+        const int64_t ss = live ? sig : 0;
+        k = lct_const(N, args.M4[4 * ss + 0], args.M4[4 * ss + 1], args.M4[4 * ss + 2], args.M4[4 * ss + 3]);
+    } else {
+        k = args.k;
+    }
+    const C<R> amp = {(R)k.amp_re, (R)k.amp_im};
+
+    const V *src = in + (size_t)(live ? sig : 0) * N;
+    V *dst = out + (size_t)(live ? sig : 0) * N;
+
+    C<R> v[E];
+    if (k.b0) {
+        // b = 0 (§1): a diagonal, no DFT.  Write it now and join the FFT
+        // with zeros so the work-group's barriers stay uniform.
+        const ThreadChirp cb = thread_chirp(k.post_hi, k.post_lo, false, t, T, N, inv2N);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = t + T * e;
+            if (live) {
+                C<R> x = ldc<R>(src + i);
+                C<R> f = cmul(chirp_at<R>(cb, e), amp);
+                stc<R>(dst + i, cmul(x, MODE == MODE_FWD ? f : cconj(f)));
+            }
+            v[e] = C<R>{(R)0, (R)0};
+        }
+    } else {
+        const ThreadChirp cin = MODE == MODE_FWD ? thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N)
+                                                 : thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = t + T * e;
+            C<R> x = live ? ldc<R>(src + i) : C<R>{(R)0, (R)0};
+            if constexpr (MODE == MODE_FWD)
+                v[e] = cmul(x, chirp_at<R>(cin, e));
+            else
+                v[e] = cmul(cconj(x), cmul(chirp_at<R>(cin, e), amp));
+        }
+    }
+
+    if constexpr (NFIX > 0)
+        fft_lds_fixed<E, NFIX>(v, lds, t);
+    else
+        fft_lds<E>(v, lds, t, T, args.sc);
+
+    if (live && !k.b0) {
+        const ThreadChirp cout = MODE == MODE_FWD ? thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N)
+                                                  : thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = t + T * e;
+            C<R> y;
+            if constexpr (MODE == MODE_FWD)
+                y = cmul(cmul(v[e], chirp_at<R>(cout, e)), amp);
+            else
+                y = cconj(cmul(v[e], chirp_at<R>(cout, e)));
+            stc<R>(dst + j, y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Parameter gradient (b != 0): G = L f and H = L(i x_k^2/(2b) f) in LDS, then
+// per-signal sums  S_H = Re sum conj(g) H,  S_G = Re sum conj(g) G,
+// S_n = Re sum conj(g) i (n_j^2 / N) G, combined into
+// dl/da = S_H, dl/db = -S_G/(2b) - (a/b) S_H + d S_n, dl/dc = 0, dl/dd = b S_n.
+// ---------------------------------------------------------------------------
+template <typename R, int E>
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_pgrad(
+    const typename Vec<R>::T *__restrict__ f, const typename Vec<R>::T *__restrict__ g,
+    double *__restrict__ grad4, LctArgs args)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    const int N = args.N;
+    const int T = args.T;
+    const Sched &sc = args.sc;
+    const int sl = (int)threadIdx.x / T;
+    const int t = (int)threadIdx.x - sl * T;
+    const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
+    const bool live = sig < args.batch;
+    C<R> *lds = smem + (size_t)sl * lds_elems(N);
+    // three FP64 accumulators per signal slot after the FFT area
+    double *acc = reinterpret_cast<double *>(smem + (size_t)args.S * lds_elems(N)) + 3 * sl;
+    const double inv2N = 0.5 / (double)N;
+    const int64_t ss = live ? sig : 0;
+    const double a = args.M4[4 * ss + 0], b = args.M4[4 * ss + 1], d = args.M4[4 * ss + 3];
+    const LctConst k = lct_const(N, a, b, args.M4[4 * ss + 2], d);
+    const V *fs = f + (size_t)ss * N;
+    const V *gs = g + (size_t)ss * N;
+    if (t == 0) {
+        acc[0] = 0.0;
+        acc[1] = 0.0;
+        acc[2] = 0.0;
+    }
+
+    // x_k^2 / (2b) = pi^2 n_k^2 / (16 b N)
+    const double qscale = PI_HI * PI_HI / (16.0 * b * (double)N);
+    double sH = 0.0, sG = 0.0, sN = 0.0;
+    C<R> v[E];
+    for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = t + T * e;
+            C<R> x = live ? ldc<R>(fs + i) : C<R>{(R)0, (R)0};
+            x = cmul(x, pre_factor<R>(k, i, N, inv2N));
+            if (pass == 0)
+                x = cmul_pi(cscale(x, (R)(qscale * nsq(i, N))));
+            v[e] = x;
+        }
+        fft_lds<E>(v, lds, t, T, sc);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = t + T * e;
+            if (!live)
+                continue;
+            C<R> y = cmul(v[e], post_factor<R>(k, j, N, inv2N));
+            C<R> gj = ldc<R>(gs + j);
+            // Re(conj(g) y)
+            double re = (double)gj.x * (double)y.x + (double)gj.y * (double)y.y;
+            if (pass == 0) {
+                sH += re;
+            } else {
+                sG += re;
+                // Re(conj(g) i y) = gj.x * (-y.y) + gj.y * y.x
+                double im = -(double)gj.x * (double)y.y + (double)gj.y * (double)y.x;
+                sN += im * nsq(j, N) / (double)N;
+            }
+        }
+    }
+    __syncthreads();
+    if (live) {
+        atomicAdd(&acc[0], sH);
+        atomicAdd(&acc[1], sG);
+        atomicAdd(&acc[2], sN);
+    }
+    __syncthreads();
+    if (live && t == 0 && b == 0.0) {
+        // the diagonal b = 0 branch of §1 is not differentiated here
+        grad4[4 * sig + 0] = 0.0;
+        grad4[4 * sig + 1] = 0.0;
+        grad4[4 * sig + 2] = 0.0;
+        grad4[4 * sig + 3] = 0.0;
+    } else if (live && t == 0) {
+        grad4[4 * sig + 0] = acc[0];
+        grad4[4 * sig + 1] = -acc[1] / (2.0 * b) - (a / b) * acc[0] + d * acc[2];
+        grad4[4 * sig + 2] = 0.0;
+        grad4[4 * sig + 3] = b * acc[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Same-grid fractional transform: length-L (L = 2N) FFT convolution
+//   g_j = C e^{-P x_j^2} sum_k T_{j-k} e^{-P x_k^2} f_k (Toeplitz) or with the
+// input reversed (Hankel).  Three FFTs in LDS: the kernel's spectrum (kept in
+// registers at the positions each thread owns after an FFT), the data's
+// spectrum, and the inverse of their product (as conj(FFT(conj(.)))).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ C<R> gauss_chirp(double mag_per, double ph_hi, double ph_lo, double m2)
+{
+    double lm = mag_per * m2;              // log modulus (<= 0)
+    double t = quad_turns(Quad{ph_hi, ph_lo}, m2);
+    C<R> c = cis_turns_from<R>(frac_turns(t));
+    R s;
+    if constexpr (sizeof(R) == 4)
+        s = expf((float)fmax(lm, -200.0));
+    else
+        s = exp(fmax(lm, -1000.0));
+    return cscale(c, s);
+}
+
+template <typename R, int E>
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frft(
+    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FrArgs args)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    const int N = args.N;
+    const int L = 2 * N;
+    const int T = args.T; // = L / E
+    const Sched &sc = args.sc;
+    const int sl = (int)threadIdx.x / T;
+    const int t = (int)threadIdx.x - sl * T;
+    const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
+    const bool live = sig < args.batch;
+    C<R> *lds = smem + (size_t)sl * lds_elems(L);
+    const int64_t ss = live ? sig : 0;
+    FrConst k = args.Z2 ? fr_const(N, args.Z2[2 * ss], args.Z2[2 * ss + 1]) : args.k;
+    const V *src = in + (size_t)ss * N;
+    V *dst = out + (size_t)ss * N;
+
+    if (k.special) {
+        // z = +-1: continuum limits (no FFT); keep the barrier pattern uniform
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const int j = t + T * e; // < N
+            if (live) {
+                C<R> x = ldc<R>(src + (k.special == 1 ? j : N - 1 - j));
+                stc<R>(dst + j, cscale(x, (R)k.cre));
+            }
+        }
+    }
+
+    // 1) kernel t_m at circular position p: m = min(p, L - p)
+    C<R> K[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t + T * e;
+        const int m = p <= N ? p : L - p;
+        const double m2 = (double)m * (double)m;
+        K[e] = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, m2);
+    }
+    fft_lds<E>(K, lds, t, T, sc);
+
+    // 2) data e^{-P x_k^2} f_k (reversed for Hankel), zero-padded to L
+    C<R> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = t + T * e;
+        C<R> x = {(R)0, (R)0};
+        if (e < E / 2 && live && !k.special) { // p < N  <=>  e < E/2
+            x = ldc<R>(src + (k.hankel ? N - 1 - p : p));
+            x = cmul(x, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(p, N)));
+        }
+        v[e] = x;
+    }
+    fft_lds<E>(v, lds, t, T, sc);
+
+    // 3) inverse DFT of the product: conj(FFT(conj(V K)))
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = cconj(cmul(v[e], K[e]));
+    fft_lds<E>(v, lds, t, T, sc);
+
+    if (live && !k.special) {
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const int j = t + T * e;
+            C<R> y = cconj(v[e]);
+            y = cmul(y, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
+            y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
+            stc<R>(dst + j, y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+template <typename R, int E, int NFIX>
+inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
+                               hipStream_t s)
+{
+    auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD> : k_lct<R, E, NFIX, MODE_ADJ>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
+                       (typename Vec<R>::T *)out, a);
+    return hipGetLastError();
+}
+
+template <typename R, int E>
+inline hipError_t launch_pgrad_t(const void *f, const void *g, double *grad4, const LctArgs &a, int nblocks,
+                                 int block, size_t lds, hipStream_t s)
+{
+    auto kern = k_lct_pgrad<R, E>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)f,
+                       (const typename Vec<R>::T *)g, grad4, a);
+    return hipGetLastError();
+}
+
+template <typename R, int E>
+inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int nblocks, int block, size_t lds,
+                                hipStream_t s)
+{
+    auto kern = k_frft<R, E>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
+                       (typename Vec<R>::T *)out, a);
+    return hipGetLastError();
+}
+
+#define LCT_E_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30)
+
+} // namespace lctk

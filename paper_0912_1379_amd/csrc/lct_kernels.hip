@@ -1,0 +1,26 @@
+// lct_kernels.hip - precision dispatch of the single-pass kernels (the
+// kernels themselves are in kernels_impl.hpp, instantiated in inst_*.hip).
+#include "lct_kernels.hpp"
+
+namespace lctk {
+
+hipError_t launch_lct(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,
+                      hipStream_t s)
+{
+    return fp64 ? dispatch_lct_f64(E, in, out, a, nb, bs, lds, s) : dispatch_lct_f32(E, in, out, a, nb, bs, lds, s);
+}
+
+hipError_t launch_pgrad(bool fp64, int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,
+                        int bs, size_t lds, hipStream_t s)
+{
+    return fp64 ? dispatch_pgrad_f64(E, f, g, grad4, a, nb, bs, lds, s)
+                : dispatch_pgrad_f32(E, f, g, grad4, a, nb, bs, lds, s);
+}
+
+hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds,
+                       hipStream_t s)
+{
+    return fp64 ? dispatch_frft_f64(E, in, out, a, nb, bs, lds, s) : dispatch_frft_f32(E, in, out, a, nb, bs, lds, s);
+}
+
+} // namespace lctk

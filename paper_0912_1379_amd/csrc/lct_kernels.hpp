@@ -1,0 +1,61 @@
+// lct_kernels.hpp - kernel argument blocks and launch entry points shared by
+// the host API (lct_api.hip) and the kernels (lct_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+#include "lct_params.hpp"
+
+namespace lctk {
+
+struct LctArgs {
+    int N;          // signal length
+    int T;          // threads per signal (N / E)
+    int S;          // signals per work-group
+    int mode;       // 0 forward, 1 adjoint
+    int64_t batch;  // number of signals
+    const double *M4; // per-signal (a, b, c, d) on the device, or null
+    LctConst k;     // constants when M4 is null
+    Sched sc;       // radix schedule of the length-N DFT
+};
+
+struct FrArgs {
+    int N;          // signal length (the convolution length is 2N)
+    int T;          // threads per signal (2N / E)
+    int S;          // signals per work-group
+    int pad_;
+    int64_t batch;
+    const double *Z2; // per-signal (re z, im z) on the device, or null
+    FrConst k;        // constants when Z2 is null
+    Sched sc;         // radix schedule of the length-2N DFT
+};
+
+// Largest work-group a kernel instantiation accepts (its launch bound): the
+// register budget per thread is 512 / (waves per SIMD) VGPRs, so larger E
+// (more values per thread) gets a smaller bound.
+__host__ __device__ constexpr int max_block(bool fp64, int E)
+{
+    return fp64 ? (E <= 8 ? 1024 : 512) : (E <= 16 ? 1024 : 512);
+}
+
+hipError_t launch_lct(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nblocks, int block,
+                      size_t lds, hipStream_t s);
+hipError_t launch_pgrad(bool fp64, int E, const void *f, const void *g, double *grad4, const LctArgs &a,
+                        int nblocks, int block, size_t lds, hipStream_t s);
+hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs &a, int nblocks, int block,
+                       size_t lds, hipStream_t s);
+
+#define LCTK_DISPATCH_DECL(tag)                                                                                    \
+    hipError_t dispatch_lct_##tag(int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,    \
+                                  hipStream_t s);                                                                    \
+    hipError_t dispatch_frft_##tag(int E, const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds,    \
+                                   hipStream_t s);                                                                   \
+    hipError_t dispatch_pgrad_##tag(int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,    \
+                                    int bs, size_t lds, hipStream_t s);
+LCTK_DISPATCH_DECL(f32)
+LCTK_DISPATCH_DECL(f64)
+#undef LCTK_DISPATCH_DECL
+
+} // namespace lctk

@@ -1,0 +1,203 @@
+// lct_params.hpp - per-signal constants of the discrete LCT and of the
+// same-grid fractional transform, derived from (a, b, c, d) or z in FP64
+// (double-double where a phase coefficient multiplies n^2 up to 2^48).
+// Shared by the host (plans) and the device (one matrix or order per signal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace lctk {
+
+// Error-free transformations: floating-point contraction is switched off in
+// each of them, since fusing a product into a following sum would change the
+// rounding these functions rely on.
+struct DD {
+    double hi, lo;
+};
+
+__host__ __device__ inline DD dd_two_prod(double a, double b)
+{
+#pragma clang fp contract(off)
+    double p = a * b;
+    return {p, fma(a, b, -p)};
+}
+__host__ __device__ inline DD dd_quick(double s, double e)
+{
+#pragma clang fp contract(off)
+    double h = s + e;
+    return {h, e - (h - s)};
+}
+__host__ __device__ inline DD dd_mul_d(DD x, double d)
+{
+#pragma clang fp contract(off)
+    DD p = dd_two_prod(x.hi, d);
+    return dd_quick(p.hi, fma(x.lo, d, p.lo));
+}
+__host__ __device__ inline DD dd_mul(DD x, DD y)
+{
+#pragma clang fp contract(off)
+    DD p = dd_two_prod(x.hi, y.hi);
+    return dd_quick(p.hi, p.lo + x.hi * y.lo + x.lo * y.hi);
+}
+__host__ __device__ inline DD dd_div_d(DD x, double d)
+{
+#pragma clang fp contract(off)
+    double q1 = x.hi / d;
+    DD r = dd_two_prod(q1, d);
+    double rem = ((x.hi - r.hi) - r.lo) + x.lo;
+    return dd_quick(q1, rem / d);
+}
+
+// pi and 1/(2 pi) as unevaluated double-double sums
+constexpr double PI_HI = 3.141592653589793;
+constexpr double PI_LO = 1.2246467991473532e-16;
+constexpr double INV2PI_HI = 0.15915494309189535;
+constexpr double INV2PI_LO = -9.839338337591243e-18;
+
+// Per-signal constants of the LCT (Algorithm steps 1-2, b != 0), or of the
+// b = 0 diagonal of §1.
+//   pre:  turns per n_k^2 of the pre-chirp a x_k^2/(2b):   a pi / (32 b N)
+//   post: turns per n_j^2 of the post-chirp d y_j^2/(2b):  b d / (2 pi N)
+//   amp:  h (2 pi i b)^(-1/2) exp(-i pi (N-1)^2 / (2N))
+// For b = 0: post holds c x_j^2/(2d) per n_j^2 (turns) and amp = sqrt(d).
+struct LctConst {
+    double pre_hi, pre_lo;
+    double post_hi, post_lo;
+    double amp_re, amp_im;
+    int b0;
+    int pad_;
+};
+
+__host__ __device__ inline LctConst lct_const(int64_t N, double a, double b, double c, double d)
+{
+    LctConst k{};
+    if (b == 0.0) {
+        // turns per n^2: c pi^2 n^2 / (8N) / (2d) / (2 pi) = c pi n^2 / (32 N d)
+        DD t = dd_div_d(dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, c), d), 32.0 * (double)N);
+        k.pre_hi = k.pre_lo = 0.0;
+        k.post_hi = t.hi;
+        k.post_lo = t.lo;
+        if (d > 0) {
+            k.amp_re = sqrt(d);
+            k.amp_im = 0.0;
+        } else {
+            k.amp_re = 0.0;
+            k.amp_im = sqrt(-d); // principal root of a negative number
+        }
+        k.b0 = 1;
+        return k;
+    }
+    // pre: a x^2/(2b) rad with x^2 = pi^2 n^2/(8N) -> a pi n^2 / (32 b N) turns
+    DD pre = dd_div_d(dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, a), b), 32.0 * (double)N);
+    // post: b d n^2 / N rad -> b d n^2 / (2 pi N) turns
+    DD post = dd_div_d(dd_mul(dd_two_prod(b, d), DD{INV2PI_HI, INV2PI_LO}), (double)N);
+    k.pre_hi = pre.hi;
+    k.pre_lo = pre.lo;
+    k.post_hi = post.hi;
+    k.post_lo = post.lo;
+    // h (2 pi i b)^(-1/2): principal root; 2 pi i b = 2 pi |b| e^{+-i pi/2}
+    double h = PI_HI / sqrt(2.0 * (double)N);
+    double mag = h / sqrt(2.0 * PI_HI * fabs(b));
+    double ph = (b > 0) ? -0.125 : 0.125; // turns: e^{-+ i pi/4}
+    // constant index phase -(N-1)^2/(4N) turns, reduced exactly
+    int64_t m = (N - 1) * (N - 1) % (4 * N);
+    ph -= (double)m / (4.0 * (double)N);
+    ph -= rint(ph);
+    k.amp_re = mag * cos(2.0 * PI_HI * ph);
+    k.amp_im = mag * sin(2.0 * PI_HI * ph);
+    k.b0 = 0;
+    return k;
+}
+
+// Per-signal constants of the same-grid fractional transform (eq. fasy with
+// y_j = x_j).  Writing the exponent as
+//   -P (x_j^2 + x_k^2) - beta (x_j -+ x_k)^2
+// with P = (1-z)/(2(1+z)), beta = z/(1-z^2) (Toeplitz, Re z >= 0) or
+// P = (1+z)/(2(1-z)), beta = -z/(1-z^2) (Hankel, Re z < 0) makes Re P >= 0
+// and Re beta >= 0, so every factor has modulus <= 1.
+//   dmag/dph: log-modulus and turns of exp(-P x^2) per n^2 (x^2 = pi^2 n^2/(8N))
+//   kmag/kph: log-modulus and turns of exp(-beta h^2 m^2) per m^2 (h^2 = pi^2/(2N))
+//   cre/cim:  h sqrt(2/(1-z^2)) / L, L = 2N the convolution length
+// special: 0 general, 1 for z = 1, 2 for z = -1 (continuum limits).
+struct FrConst {
+    double dmag, dph_hi, dph_lo;
+    double kmag, kph_hi, kph_lo;
+    double cre, cim;
+    int hankel;
+    int special;
+};
+
+__host__ __device__ inline void cdiv(double ar, double ai, double br, double bi, double &qr, double &qi)
+{
+    // Smith's algorithm
+    if (fabs(br) >= fabs(bi)) {
+        double r = bi / br, den = br + bi * r;
+        qr = (ar + ai * r) / den;
+        qi = (ai - ar * r) / den;
+    } else {
+        double r = br / bi, den = br * r + bi;
+        qr = (ar * r + ai) / den;
+        qi = (ai * r - ar) / den;
+    }
+}
+
+__host__ __device__ inline void csqrt_principal(double re, double im, double &sr, double &si)
+{
+    double m = hypot(re, im);
+    if (m == 0.0) {
+        sr = si = 0.0;
+        return;
+    }
+    if (re >= 0) {
+        sr = sqrt(0.5 * (m + re));
+        si = im / (2.0 * sr);
+    } else {
+        si = copysign(sqrt(0.5 * (m - re)), im);
+        sr = im / (2.0 * si);
+    }
+}
+
+__host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
+{
+    FrConst k{};
+    if (zi == 0.0 && (zr == 1.0 || zr == -1.0)) {
+        k.special = zr > 0 ? 1 : 2;
+        k.cre = sqrt(2.0 * PI_HI);
+        return k;
+    }
+    k.special = 0;
+    k.hankel = zr < 0.0 ? 1 : 0;
+    double s = k.hankel ? -1.0 : 1.0; // z -> s z maps the Hankel case onto the Toeplitz formulas
+    double wr = s * zr, wi = s * zi;
+    // P = (1 - w) / (2 (1 + w)), beta = w / (1 - w^2)  (w^2 = z^2)
+    double Pr, Pi;
+    cdiv(1.0 - wr, -wi, 2.0 * (1.0 + wr), 2.0 * wi, Pr, Pi);
+    double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+    double omr = 1.0 - z2r, omi = -z2i;
+    double Br, Bi;
+    cdiv(wr, wi, omr, omi, Br, Bi);
+    const double n = (double)N;
+    // exp(-P x^2), x^2 = pi^2 n^2 / (8N)
+    k.dmag = -Pr * PI_HI * PI_HI / (8.0 * n);
+    DD dph = dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, -Pi), 16.0 * n); // -Im P pi^2/(8N) / (2 pi)
+    k.dph_hi = dph.hi;
+    k.dph_lo = dph.lo;
+    // exp(-beta h^2 m^2), h^2 = pi^2 / (2N)
+    k.kmag = -Br * PI_HI * PI_HI / (2.0 * n);
+    DD kph = dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, -Bi), 4.0 * n); // -Im beta pi^2/(2N) / (2 pi)
+    k.kph_hi = kph.hi;
+    k.kph_lo = kph.lo;
+    // h sqrt(2 / (1 - z^2)) / (2N)
+    double qr, qi;
+    cdiv(2.0, 0.0, omr, omi, qr, qi);
+    double sr, si;
+    csqrt_principal(qr, qi, sr, si);
+    double h = PI_HI / sqrt(2.0 * n);
+    k.cre = h * sr / (2.0 * n);
+    k.cim = h * si / (2.0 * n);
+    return k;
+}
+
+} // namespace lctk

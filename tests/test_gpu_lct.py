@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element
+by element on the same seeded inputs.
+
+Bounds: relative L2 error per signal <= 2e-5 for the FP32 path and <= 1e-12
+for the FP64 path (LCT), the bounds stated for the method's FP32 / FP64
+variants at N = 4096; the same bounds are applied at every size here.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_0912_1379_amd as lct
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 2e-5, torch.complex128: 1e-12}
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rows(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    gpu = np.atleast_2d(gpu)
+    ref = np.atleast_2d(ref)
+    return np.linalg.norm(gpu - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+
+
+def c1_inputs(N, batch, seed):
+    g = np.random.default_rng(seed)
+    M = workloads.sl2_params(batch, g)
+    gp = workloads.gaussian_params(batch, g)
+    f = workloads.chirped_gaussians(oracle.nodes(N), gp)
+    return M, f
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+SIZES32 = [1, 2, 3, 4, 5, 8, 12, 16, 30, 64, 96, 100, 128, 250, 256, 384, 1000, 1024, 1536, 2048, 3000,
+           4096, 5120, 6144, 8192, 10240, 12288, 15360, 16384]
+SIZES64 = [1, 2, 3, 8, 30, 128, 1000, 1024, 3000, 4096, 6144, 8192]
+
+
+def check_many(N, dtype, batch=3, seed=0, rows=None):
+    M, f = c1_inputs(N, batch, 100 + N + seed)
+    x = dev(f, dtype)
+    M4 = dev(M, torch.float64)
+    y = lct.lct_exec_many(x, M4)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().astype(np.complex128)
+    fin = x.cpu().numpy().astype(np.complex128)  # the oracle sees the cast input
+    for s in range(batch):
+        if rows is None:
+            ref = oracle.lct(fin[s], *M[s])
+            got = yh[s]
+        else:
+            ref = oracle.lct(fin[s], *M[s], rows=rows)
+            got = yh[s][rows]
+        e = rel_rows(got, ref)[0]
+        assert e <= TOL[dtype], (N, s, M[s], e)
+
+
+@pytest.mark.parametrize("N", SIZES32)
+def test_lct_many_fp32(N):
+    rows = None if N <= 4096 else np.random.default_rng(N).choice(N, 192, replace=False)
+    check_many(N, torch.complex64, rows=rows)
+
+
+@pytest.mark.parametrize("N", SIZES64)
+def test_lct_many_fp64(N):
+    rows = None if N <= 4096 else np.random.default_rng(N).choice(N, 128, replace=False)
+    check_many(N, torch.complex128, rows=rows)
+
+
+@pytest.mark.parametrize("dtype,prec", [(torch.complex128, lct.LCT_FP64), (torch.complex64, lct.LCT_FP32)])
+@pytest.mark.parametrize("M", [(0.5, 1.0, -0.5, 1.0), (0.0, 1.0, -1.0, 0.0)])
+def test_single_signal_hermite_sum(dtype, prec, M):
+    """N = 128, sum of the first 8 Hermite functions with seeded complex
+    coefficients, on a plan (one matrix)."""
+    N = 128
+    f, _ = workloads.hermite_sum(oracle.nodes(N))
+    p = lct.lct_plan_create(N, *M, precision=prec)
+    x = dev(f[None, :], dtype)
+    y = lct.lct_exec(p, x)
+    fin = x.cpu().numpy().astype(np.complex128)[0]
+    ref = oracle.lct(fin, *M)
+    assert rel_rows(y.cpu().numpy()[0], ref)[0] <= TOL[dtype]
+
+
+def test_full_size_batch_sampled():
+    """4096 signals x N = 4096, one matrix per signal, in the configuration the
+    benchmark times; 8 signals x 256 outputs checked against the oracle."""
+    N, B = 4096, 4096
+    g = workloads.rng(1)
+    M = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    x = dev(workloads.chirped_gaussians(oracle.nodes(N), gp), torch.complex64)
+    M4 = dev(M, torch.float64)
+    y = lct.lct_exec_many(x, M4)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(7).choice(B, 8, replace=False)
+    rows = np.sort(np.random.default_rng(8).choice(N, 256, replace=False))
+    for s in pick:
+        fin = x[s].cpu().numpy().astype(np.complex128)
+        ref = oracle.lct(fin, *M[s], rows=rows)
+        got = y[s].cpu().numpy()[rows]
+        assert rel_rows(got, ref)[0] <= 2e-5, (s, M[s])
+
+
+def test_in_place_and_stream():
+    N = 1024
+    M, f = c1_inputs(N, 4, 5)
+    x = dev(f, torch.complex64)
+    M4 = dev(M, torch.float64)
+    ref = lct.lct_exec_many(x, M4).cpu()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        y = lct.lct_exec_many(x, M4, out=x)  # in place
+    s.synchronize()
+    assert y.data_ptr() == x.data_ptr()
+    assert torch.equal(y.cpu(), ref)
+
+
+def test_deterministic_repeat():
+    N = 4096
+    M, f = c1_inputs(N, 64, 6)
+    x = dev(f, torch.complex64)
+    M4 = dev(M, torch.float64)
+    a = lct.lct_exec_many(x, M4)
+    b = lct.lct_exec_many(x, M4)
+    assert torch.equal(a, b)
+
+
+def test_empty_batch():
+    x = torch.empty((0, 64), dtype=torch.complex64, device="cuda")
+    M4 = torch.empty((0, 4), dtype=torch.float64, device="cuda")
+    assert lct.lct_exec_many(x, M4).shape == (0, 64)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_b_zero_rows(dtype):
+    """Rows with b = 0 take the diagonal of §1, mixed with b != 0 rows."""
+    N = 256
+    M, f = c1_inputs(N, 6, 9)
+    M[1] = [2.0, 0.0, 0.7, 0.5]
+    M[4] = [-0.5, 0.0, 1.2, -2.0]
+    x = dev(f, dtype)
+    y = lct.lct_exec_many(x, dev(M, torch.float64)).cpu().numpy()
+    fin = x.cpu().numpy().astype(np.complex128)
+    for s in range(6):
+        assert rel_rows(y[s], oracle.lct(fin[s], *M[s]))[0] <= TOL[dtype], s
+    p = lct.lct_plan_create(N, 2.0, 0.0, 0.7, 0.5, precision=lct.LCT_FP64 if dtype == torch.complex128 else 0)
+    y0 = lct.lct_exec(p, x).cpu().numpy()
+    assert rel_rows(y0[0], oracle.lct(fin[0], 2.0, 0.0, 0.7, 0.5))[0] <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("N", [16, 100, 1024, 4096])
+def test_adjoint(dtype, N):
+    M, f = c1_inputs(N, 3, 11)
+    g = dev(f, dtype)
+    out = lct.lct_exec_many_adjoint(g, dev(M, torch.float64)).cpu().numpy()
+    gin = g.cpu().numpy().astype(np.complex128)
+    for s in range(3):
+        ref = oracle.lct_adjoint(gin[s], *M[s])
+        assert rel_rows(out[s], ref)[0] <= TOL[dtype], s
+    p = lct.lct_plan_create(N, *M[0], precision=lct.LCT_FP64 if dtype == torch.complex128 else 0)
+    o1 = lct.lct_exec_adjoint(p, g[:1].contiguous()).cpu().numpy()
+    assert rel_rows(o1[0], oracle.lct_adjoint(gin[0], *M[0]))[0] <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 2e-4), (torch.complex128, 1e-10)])
+@pytest.mark.parametrize("N", [64, 256, 2048])
+def test_param_grad(dtype, tol, N):
+    M, f = c1_inputs(N, 3, 13)
+    gen = np.random.default_rng(N)
+    gg = gen.standard_normal((3, N)) + 1j * gen.standard_normal((3, N))
+    fx, gx = dev(f, dtype), dev(gg, dtype)
+    d = lct.lct_param_grad_many(fx, gx, dev(M, torch.float64)).cpu().numpy()
+    fin = fx.cpu().numpy().astype(np.complex128)
+    gin = gx.cpu().numpy().astype(np.complex128)
+    for s in range(3):
+        ref = oracle.lct_param_grad(fin[s], gin[s], *M[s])
+        assert np.abs(d[s] - ref).max() <= tol * np.abs(ref).max(), (s, d[s], ref)
+        assert d[s][2] == 0.0
+
+
+ZS = [0.5, 0.6 * np.exp(-1.1j), -0.7 + 0.2j, 0.9 * np.exp(2.5j), 1j, -1j, np.exp(0.8j), 0.3j, 0.98, 1.0, -1.0]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 2e-5), (torch.complex128, 1e-11)])
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 100, 1000, 4096])
+def test_frft(dtype, tol, N):
+    x_n = oracle.nodes(N)
+    gen = np.random.default_rng(N)
+    gp = workloads.gaussian_params(len(ZS), gen)
+    f = workloads.chirped_gaussians(x_n, gp)
+    x = dev(f, dtype)
+    Z2 = dev(np.stack([np.real(ZS), np.imag(ZS)], axis=1), torch.float64)
+    y = lct.frft_exec_many(x, Z2).cpu().numpy()
+    fin = x.cpu().numpy().astype(np.complex128)
+    for s, z in enumerate(ZS):
+        ref = oracle.frft(fin[s], z)
+        assert rel_rows(y[s], ref)[0] <= tol, (N, z)
+
+
+def test_frft_plan_and_large():
+    N = 8192
+    x_n = oracle.nodes(N)
+    gp = workloads.gaussian_params(2, np.random.default_rng(3))
+    x = dev(workloads.chirped_gaussians(x_n, gp), torch.complex64)
+    p = lct.lct_plan_create(N, 1.0, 1.0, 0.0, 1.0)
+    z = 0.8 * np.exp(-0.6j)
+    y = lct.frft_exec(p, z, x).cpu().numpy()
+    fin = x.cpu().numpy().astype(np.complex128)
+    rows = np.random.default_rng(4).choice(N, 128, replace=False)
+    for s in range(2):
+        assert rel_rows(y[s][rows], oracle.frft(fin[s], z, rows=rows))[0] <= 2e-5
+
+
+def test_autograd_matches_oracle():
+    N, B = 256, 4
+    M, f = c1_inputs(N, B, 17)
+    x = dev(f, torch.complex128).requires_grad_(True)
+    M4 = dev(M, torch.float64).requires_grad_(True)
+    y = lct.lct(x, M4)
+    I = torch.rand(B, N, dtype=torch.float64, device="cuda") * 0.1
+    loss = ((y.abs() ** 2 - I) ** 2).sum()
+    loss.backward()
+    gy = (4 * (y.abs() ** 2 - I) * y).detach().cpu().numpy()
+    fin = f
+    for s in range(B):
+        gf_ref = oracle.lct_adjoint(gy[s], *M[s])
+        assert rel_rows(x.grad[s].cpu().numpy(), gf_ref)[0] < 1e-11
+        gm_ref = oracle.lct_param_grad(fin[s], gy[s], *M[s])
+        gm = M4.grad[s].cpu().numpy()
+        assert np.abs(gm - gm_ref).max() <= 1e-9 * np.abs(gm_ref).max()
+
+
+def test_error_codes_on_device_buffers():
+    x = torch.zeros(2, 64, dtype=torch.complex64, device="cuda")
+    M4 = torch.zeros(2, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(lct.LctError):
+        lct.lct_exec_many(x[:, :63].contiguous(), M4)  # N = 63 unsupported
+    p = lct.lct_plan_create(64, 1.0, 1.0, 0.0, 1.0)
+    with pytest.raises(lct.LctError):
+        lct.frft_exec(p, 1.5, x)
+    with pytest.raises(TypeError):
+        lct.lct_exec(p, x.to(torch.complex128))
