@@ -54,7 +54,9 @@ def make_inputs(B: int, N: int, seed_index: int = 1):
 
 
 def time_launches(fn, steps: int, warmup: int):
-    """Average duration of one call, from HIP events on the current stream."""
+    """Times `steps` calls on the current stream (the stream the library
+    launches on).  Returns (ms per step over the whole timed region, mean ms
+    of the launch itself from an event pair around each call, wall seconds)."""
     import torch
 
     for _ in range(warmup):
@@ -62,14 +64,18 @@ def time_launches(fn, steps: int, warmup: int):
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     start.record()
-    for _ in range(steps):
+    for a, b in ev:
+        a.record()
         fn()
+        b.record()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(stop) / steps, wall
+    per_launch = sum(a.elapsed_time(b) for a, b in ev) / steps
+    return start.elapsed_time(stop) / steps, per_launch, wall
 
 
 def cpu_baseline(xh: np.ndarray, M: np.ndarray, yh: np.ndarray, budget_s: float):
@@ -127,20 +133,22 @@ def main():
     def step32():
         lct.lct_exec_many(x32, M4, out=y32)
 
-    ms, wall = time_launches(step32, args.steps, args.warmup)
+    ms, ms_kernel, wall = time_launches(step32, args.steps, args.warmup)
     samples = B * N
     value = samples / (ms * 1e-3)
     algo_bytes = 16.0 * samples
-    achieved_gbps = algo_bytes / (ms * 1e-3) / 1e9
-    print(f"[bench] fp32: {ms * 1e3:.1f} us/step, {achieved_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+    achieved_gbps = algo_bytes / (ms_kernel * 1e-3) / 1e9
+    print(f"[bench] fp32: {ms * 1e3:.1f} us/step, kernel {ms_kernel * 1e3:.1f} us, {achieved_gbps:.0f} GB/s",
+          file=sys.stderr, flush=True)
 
     fp64 = None
     if not args.no_fp64:
         x64 = x32.to(torch.complex128)
         y64 = torch.empty_like(x64)
-        ms64, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64), max(5, args.steps // 2), 3)
+        ms64, ms64_kernel, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64),
+                                              max(5, args.steps // 2), 3)
         fp64 = {"ms_per_step": ms64, "value": samples / (ms64 * 1e-3),
-                "achieved_GBps": 32.0 * samples / (ms64 * 1e-3) / 1e9,
+                "kernel_ms": ms64_kernel, "achieved_GBps": 32.0 * samples / (ms64_kernel * 1e-3) / 1e9,
                 "fp32_speedup": ms64 / ms}
         print(f"[bench] fp64: {ms64 * 1e3:.1f} us/step", file=sys.stderr, flush=True)
         del x64, y64
@@ -168,7 +176,9 @@ def main():
                                "chirped-Gaussian inputs", "signals": B, "N": N, "precision": "fp32",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved_gbps / PEAK_HBM_GBPS, "traffic": traffic},
+                     "frac": achieved_gbps / PEAK_HBM_GBPS, "traffic": traffic,
+                     "kernel": "k_lct<float,16,4096,fwd>", "kernel_ms": ms_kernel,
+                     "algorithmic_bytes_per_launch": algo_bytes},
         "wall_s_timed": wall,
         "fp64_path": fp64,
     }

@@ -47,11 +47,11 @@ struct ThreadChirp {
 };
 
 __device__ __forceinline__ ThreadChirp thread_chirp(double qhi, double qlo, bool with_index, int t, int T, int N,
-                                                    double inv2N)
+                                                    double inv2N, double extra_turns = 0.0)
 {
     const Quad q{qhi, qlo};
     const double nt = (double)(2 * t - N + 1);
-    double A = quad_turns(q, nt * nt);
+    double A = quad_turns(q, nt * nt) + extra_turns;
     double B = quad_turns(q, 4.0 * (double)T * nt);
     double C = quad_turns(q, 4.0 * (double)T * (double)T);
     if (with_index) {
@@ -86,51 +86,67 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
     const int N = NFIX > 0 ? NFIX : args.N;
     const int T = NFIX > 0 ? NFIX / E : args.T;
 
-    const int sl = (int)threadIdx.x / T; // signal slot within the work-group
+    // With T >= 256 threads per signal the host launches one signal per
+    // work-group; saying so at compile time keeps the signal index uniform
+    // (scalar loads of its parameters).
+    constexpr bool ONE = NFIX > 0 && NFIX / E >= 256;
+    const int sl = ONE ? 0 : (int)threadIdx.x / T; // signal slot within the work-group
     const int t = (int)threadIdx.x - sl * T;
     const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
     const bool live = sig < args.batch;
     C<R> *lds = smem + (size_t)sl * lds_elems(N);
     const double inv2N = 0.5 / (double)N;
 
-    LctConst k;
+    // Per-signal matrix, loaded before the samples so that waiting for it
+    // does not wait for them.
+    double m4[4] = {0.0, 0.0, 0.0, 0.0};
     if (args.M4 != nullptr) {
         const int64_t ss = live ? sig : 0;
-        k = lct_const(N, args.M4[4 * ss + 0], args.M4[4 * ss + 1], args.M4[4 * ss + 2], args.M4[4 * ss + 3]);
-    } else {
-        k = args.k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            m4[q] = args.M4[4 * ss + q];
     }
-    const C<R> amp = {(R)k.amp_re, (R)k.amp_im};
 
-    const V *src = in + (size_t)(live ? sig : 0) * N;
-    V *dst = out + (size_t)(live ? sig : 0) * N;
+    // One buffer descriptor per work-group covering its live signals; thread
+    // t of slot sl reads/writes element t + T e at voff + e * (T * sizeof(V)).
+    const int64_t first = (int64_t)blockIdx.x * args.S;
+    const int64_t nlive = args.batch - first < args.S ? args.batch - first : args.S;
+    const uint32_t wg_bytes = (uint32_t)(nlive * N * (int64_t)sizeof(V));
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(in + first * N, wg_bytes);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(out + first * N, wg_bytes);
+    const int voff = (sl * N + t) * (int)sizeof(V);
+    const int sstep = T * (int)sizeof(V);
 
+    // Issue every load first: the per-signal constants below are computed
+    // while the samples are in flight.
     C<R> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = Buf<R>::load(rin, voff, e * sstep);
+
+    const LctConst k = args.M4 != nullptr ? lct_const_from(args.nc, m4[0], m4[1], m4[2], m4[3]) : args.k;
+    const R mag = (R)k.amp_mag;
+
     if (k.b0) {
         // b = 0 (§1): a diagonal, no DFT.  Write it now and join the FFT
         // with zeros so the work-group's barriers stay uniform.
-        const ThreadChirp cb = thread_chirp(k.post_hi, k.post_lo, false, t, T, N, inv2N);
+        const ThreadChirp cb = thread_chirp(k.post_hi, k.post_lo, false, t, T, N, inv2N, k.amp_turns);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = t + T * e;
-            if (live) {
-                C<R> x = ldc<R>(src + i);
-                C<R> f = cmul(chirp_at<R>(cb, e), amp);
-                stc<R>(dst + i, cmul(x, MODE == MODE_FWD ? f : cconj(f)));
-            }
+            C<R> f = cscale(chirp_at<R>(cb, e), mag);
+            Buf<R>::store(cmul(v[e], MODE == MODE_FWD ? f : cconj(f)), rout, voff, e * sstep);
             v[e] = C<R>{(R)0, (R)0};
         }
     } else {
-        const ThreadChirp cin = MODE == MODE_FWD ? thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N)
-                                                 : thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N);
+        const ThreadChirp cin = MODE == MODE_FWD
+                                    ? thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N)
+                                    : thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = t + T * e;
-            C<R> x = live ? ldc<R>(src + i) : C<R>{(R)0, (R)0};
             if constexpr (MODE == MODE_FWD)
-                v[e] = cmul(x, chirp_at<R>(cin, e));
+                v[e] = cmul(v[e], chirp_at<R>(cin, e));
             else
-                v[e] = cmul(cconj(x), cmul(chirp_at<R>(cin, e), amp));
+                v[e] = cscale(cmul(cconj(v[e]), chirp_at<R>(cin, e)), mag);
         }
     }
 
@@ -140,17 +156,17 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
         fft_lds<E>(v, lds, t, T, args.sc);
 
     if (live && !k.b0) {
-        const ThreadChirp cout = MODE == MODE_FWD ? thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N)
-                                                  : thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N);
+        const ThreadChirp cout = MODE == MODE_FWD
+                                     ? thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns)
+                                     : thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int j = t + T * e;
             C<R> y;
             if constexpr (MODE == MODE_FWD)
-                y = cmul(cmul(v[e], chirp_at<R>(cout, e)), amp);
+                y = cscale(cmul(v[e], chirp_at<R>(cout, e)), mag);
             else
                 y = cconj(cmul(v[e], chirp_at<R>(cout, e)));
-            stc<R>(dst + j, y);
+            Buf<R>::store(y, rout, voff, e * sstep);
         }
     }
 }
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_pgrad(
     const double inv2N = 0.5 / (double)N;
     const int64_t ss = live ? sig : 0;
     const double a = args.M4[4 * ss + 0], b = args.M4[4 * ss + 1], d = args.M4[4 * ss + 3];
-    const LctConst k = lct_const(N, a, b, args.M4[4 * ss + 2], d);
+    const LctConst k = lct_const_from(args.nc, a, b, args.M4[4 * ss + 2], d);
     const V *fs = f + (size_t)ss * N;
     const V *gs = g + (size_t)ss * N;
     if (t == 0) {

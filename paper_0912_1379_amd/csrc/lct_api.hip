@@ -178,6 +178,7 @@ int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode,
     a.M4 = M4;
     if (k)
         a.k = *k;
+    a.nc = n_const_host(N);
     a.sc = tl.sc;
     int64_t nb = (batch + tl.S - 1) / tl.S;
     if (nb > INT32_MAX)
@@ -329,6 +330,7 @@ int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const v
     a.mode = 0;
     a.batch = batch;
     a.M4 = M4;
+    a.nc = n_const_host(N);
     a.sc = tl.sc;
     int64_t nb = (batch + tl.S - 1) / tl.S;
     if (nb > INT32_MAX)

@@ -18,6 +18,7 @@ struct LctArgs {
     int64_t batch;  // number of signals
     const double *M4; // per-signal (a, b, c, d) on the device, or null
     LctConst k;     // constants when M4 is null
+    NConst nc;      // N-only constants (per-signal constants derive from them)
     Sched sc;       // radix schedule of the length-N DFT
 };
 

@@ -62,10 +62,13 @@ constexpr double INV2PI_LO = -9.839338337591243e-18;
 //   post: turns per n_j^2 of the post-chirp d y_j^2/(2b):  b d / (2 pi N)
 //   amp:  h (2 pi i b)^(-1/2) exp(-i pi (N-1)^2 / (2N))
 // For b = 0: post holds c x_j^2/(2d) per n_j^2 (turns) and amp = sqrt(d).
+// The amplitude is also kept in polar form (amp_mag, amp_turns) so that
+// kernels can fold its phase into the post-chirp.
 struct LctConst {
     double pre_hi, pre_lo;
     double post_hi, post_lo;
     double amp_re, amp_im;
+    double amp_mag, amp_turns;
     int b0;
     int pad_;
 };
@@ -86,6 +89,8 @@ __host__ __device__ inline LctConst lct_const(int64_t N, double a, double b, dou
             k.amp_re = 0.0;
             k.amp_im = sqrt(-d); // principal root of a negative number
         }
+        k.amp_mag = sqrt(fabs(d));
+        k.amp_turns = d > 0 ? 0.0 : 0.25;
         k.b0 = 1;
         return k;
     }
@@ -107,6 +112,83 @@ __host__ __device__ inline LctConst lct_const(int64_t N, double a, double b, dou
     ph -= rint(ph);
     k.amp_re = mag * cos(2.0 * PI_HI * ph);
     k.amp_im = mag * sin(2.0 * PI_HI * ph);
+    k.amp_mag = mag;
+    k.amp_turns = ph;
+    k.b0 = 0;
+    return k;
+}
+
+// Constants of the LCT that depend only on N, derived once on the host in
+// extended precision so that a kernel holding one matrix per signal only
+// needs a few FP64 operations per signal (lct_const_from):
+//   pre:  pi / (32 N)   turns per n^2 and per unit of a/b
+//   post: 1 / (2 pi N)  turns per n^2 and per unit of b d
+//   hs:   h / sqrt(2 pi),  h = pi / sqrt(2N)
+//   cpos/cneg: e^{-+i pi/4} e^{-i pi (N-1)^2/(2N)}, the phase of
+//         h (2 pi i b)^(-1/2) e^{-i pi (N-1)^2/(2N)} for b > 0 / b < 0
+struct NConst {
+    double pre_hi, pre_lo;
+    double post_hi, post_lo;
+    double hs;
+    double cpos_re, cpos_im;
+    double cneg_re, cneg_im;
+    double tpos, tneg; // the same two phases in turns
+};
+
+inline NConst n_const_host(int64_t N)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double n = (long double)N;
+    NConst c{};
+    long double pre = pi / (32.0L * n);
+    long double post = 1.0L / (2.0L * pi * n);
+    c.pre_hi = (double)pre;
+    c.pre_lo = (double)(pre - (long double)c.pre_hi);
+    c.post_hi = (double)post;
+    c.post_lo = (double)(post - (long double)c.post_hi);
+    c.hs = (double)((pi / sqrtl(2.0L * n)) / sqrtl(2.0L * pi));
+    // constant index phase -(N-1)^2/(4N) turns, reduced exactly
+    int64_t m = (N - 1) * (N - 1) % (4 * N);
+    long double base = -(long double)m / (4.0L * n);
+    long double tp = base - 0.125L, tn = base + 0.125L;
+    c.cpos_re = (double)cosl(2.0L * pi * tp);
+    c.cpos_im = (double)sinl(2.0L * pi * tp);
+    c.cneg_re = (double)cosl(2.0L * pi * tn);
+    c.cneg_im = (double)sinl(2.0L * pi * tn);
+    c.tpos = (double)(tp - roundl(tp));
+    c.tneg = (double)(tn - roundl(tn));
+    return c;
+}
+
+// Per-signal LCT constants from the N-only constants: same values as
+// lct_const, without transcendental functions.
+__host__ __device__ inline LctConst lct_const_from(const NConst &nc, double a, double b, double c, double d)
+{
+    LctConst k{};
+    const DD pre{nc.pre_hi, nc.pre_lo};
+    if (b == 0.0) {
+        // c x^2 / (2d) rad = c pi n^2 / (32 N d) turns
+        DD t = dd_div_d(dd_mul_d(pre, c), d);
+        k.post_hi = t.hi;
+        k.post_lo = t.lo;
+        k.amp_re = d > 0 ? sqrt(d) : 0.0;
+        k.amp_im = d > 0 ? 0.0 : sqrt(-d);
+        k.amp_mag = sqrt(fabs(d));
+        k.amp_turns = d > 0 ? 0.0 : 0.25;
+        k.b0 = 1;
+        return k;
+    }
+    DD p = dd_div_d(dd_mul_d(pre, a), b);
+    DD q = dd_mul_d(dd_mul_d(DD{nc.post_hi, nc.post_lo}, b), d);
+    k.pre_hi = p.hi;
+    k.pre_lo = p.lo;
+    k.post_hi = q.hi;
+    k.post_lo = q.lo;
+    const double mag = nc.hs / sqrt(fabs(b));
+    k.amp_re = mag * (b > 0 ? nc.cpos_re : nc.cneg_re);
+    k.amp_im = mag * (b > 0 ? nc.cpos_im : nc.cneg_im);
+    k.amp_mag = mag;
+    k.amp_turns = b > 0 ? nc.tpos : nc.tneg;
     k.b0 = 0;
     return k;
 }
