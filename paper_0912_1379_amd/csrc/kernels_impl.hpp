@@ -61,6 +61,23 @@ __device__ __forceinline__ ThreadChirp thread_chirp(double qhi, double qlo, bool
     return {frac_turns(A), frac_turns(B), frac_turns(C)};
 }
 
+// Same polynomial for the positions i_e = i0 + D e (any stride D):
+// n_e = n_{i0} + 2 D e.  Needs |n| < 2^24 so that every product is exact.
+__device__ __forceinline__ ThreadChirp seq_chirp(double qhi, double qlo, bool with_index, int i0, int D, int N,
+                                                 double inv2N, double extra_turns = 0.0)
+{
+    const Quad q{qhi, qlo};
+    const double n0 = (double)(2 * i0 - N + 1);
+    double A = quad_turns(q, n0 * n0) + extra_turns;
+    double B = quad_turns(q, 4.0 * (double)D * n0);
+    double C = quad_turns(q, 4.0 * (double)D * (double)D);
+    if (with_index) {
+        A += index_turns(i0, N, inv2N);
+        B += index_turns(D, N, inv2N);
+    }
+    return {frac_turns(A), frac_turns(B), frac_turns(C)};
+}
+
 template <typename R>
 __device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
 {

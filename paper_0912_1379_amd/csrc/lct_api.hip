@@ -130,6 +130,111 @@ Tiling make_tiling(int64_t Nfft, bool fp64, bool frft, size_t extra)
     return t;
 }
 
+int hip_status(hipError_t e);
+
+// Two-pass (four-step) plan for N beyond one work-group: N = N1 N2 with N1 the
+// largest divisor <= sqrt(N) whose tiles fit; C columns per pass-1 group and
+// RR rows per pass-2 group, as many as keep >= 128-byte row segments and fit
+// LDS and the launch bound.
+struct FsTiling {
+    int N1 = 0, N2 = 0, E1 = 0, E2 = 0, T1 = 0, T2 = 0, C = 0, RR = 0, bs1 = 0, bs2 = 0;
+    size_t lds1 = 0, lds2 = 0;
+    Sched sc1{}, sc2{};
+    bool ok = false;
+};
+
+int pick_group(int Nsub, int T, int E, int other, bool fp64)
+{
+    const size_t elem = fp64 ? 16 : 8;
+    const size_t per = (size_t)lds_elems(Nsub) * elem;
+    const int want = fp64 ? 8 : 16;          // >= 128 B per row segment
+    int cap = 256 / T > want ? 256 / T : want; // ~256 threads when T is small
+    if (cap > 64)
+        cap = 64;
+    for (int c = cap; c >= 1; --c) {
+        if (other % c)
+            continue;
+        if (c * T > max_block(fp64, E) || c * per > LDS_BYTES)
+            continue;
+        return c;
+    }
+    return 0;
+}
+
+FsTiling make_fs(int64_t N, bool fp64)
+{
+    FsTiling f;
+    int64_t best = 0;
+    for (int64_t d = 1; d * d <= N; ++d)
+        if (N % d == 0)
+            best = d;
+    for (int64_t N1 = best; N1 >= 2; --N1) {
+        if (N % N1)
+            continue;
+        const int64_t N2 = N / N1;
+        if (N1 > 16384 || N2 > 16384)
+            break;
+        f.N1 = (int)N1;
+        f.N2 = (int)N2;
+        f.E1 = choose_E(N1, fp64, false);
+        f.E2 = choose_E(N2, fp64, false);
+        if (!f.E1 || !f.E2)
+            continue;
+        f.T1 = (int)(N1 / f.E1);
+        f.T2 = (int)(N2 / f.E2);
+        f.sc1 = make_sched(N1, f.E1);
+        f.sc2 = make_sched(N2, f.E2);
+        if (f.sc1.nst < 0 || f.sc2.nst < 0)
+            continue;
+        f.C = pick_group((int)N1, f.T1, f.E1, (int)N2, fp64);
+        f.RR = pick_group((int)N2, f.T2, f.E2, (int)N1, fp64);
+        if (!f.C || !f.RR)
+            continue;
+        const size_t elem = fp64 ? 16 : 8;
+        f.bs1 = f.C * f.T1;
+        f.bs2 = f.RR * f.T2;
+        f.lds1 = (size_t)f.C * lds_elems((int)N1) * elem;
+        f.lds2 = (size_t)f.RR * lds_elems((int)N2) * elem;
+        f.ok = true;
+        return f;
+    }
+    f.ok = false;
+    return f;
+}
+
+int fs_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
+           int64_t batch, hipStream_t s)
+{
+    if (in == out)
+        return LCT_ERR_ARG; // pass 1 reads columns of `in` while writing rows of `out`
+    FsTiling f = make_fs(N, fp64);
+    if (!f.ok)
+        return LCT_ERR_UNSUPPORTED;
+    FsArgs a{};
+    a.N = (int)N;
+    a.N1 = f.N1;
+    a.N2 = f.N2;
+    a.C = f.C;
+    a.RR = f.RR;
+    a.T1 = f.T1;
+    a.T2 = f.T2;
+    a.mode = mode;
+    a.batch = batch;
+    a.M4 = M4;
+    if (k)
+        a.k = *k;
+    a.nc = n_const_host(N);
+    a.sc1 = f.sc1;
+    a.sc2 = f.sc2;
+    const int64_t nb1 = batch * (f.N2 / f.C), nb2 = batch * (f.N1 / f.RR);
+    if (nb1 > INT32_MAX || nb2 > INT32_MAX)
+        return LCT_ERR_ARG;
+    hipError_t e = launch_fs1(fp64, f.E1, in, out, a, (int)nb1, f.bs1, f.lds1, s);
+    if (e != hipSuccess)
+        return LCT_ERR_HIP;
+    return hip_status(launch_fs2(fp64, f.E2, out, a, (int)nb2, f.bs2, f.lds2, s));
+}
+
 int check_ptr(const void *p, bool fp64)
 {
     if (p == nullptr)
@@ -165,7 +270,7 @@ int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode,
     if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
         return rc;
     if (N > lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
-        return LCT_ERR_UNSUPPORTED;
+        return fs_run(N, fp64, M4, k, mode, in, out, batch, s);
     Tiling tl = make_tiling(N, fp64, false, 0);
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;

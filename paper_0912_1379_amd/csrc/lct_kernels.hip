@@ -23,4 +23,15 @@ hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs
     return fp64 ? dispatch_frft_f64(E, in, out, a, nb, bs, lds, s) : dispatch_frft_f32(E, in, out, a, nb, bs, lds, s);
 }
 
+hipError_t launch_fs1(bool fp64, int E, const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds,
+                      hipStream_t s)
+{
+    return fp64 ? dispatch_fs1_f64(E, in, out, a, nb, bs, lds, s) : dispatch_fs1_f32(E, in, out, a, nb, bs, lds, s);
+}
+
+hipError_t launch_fs2(bool fp64, int E, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
+{
+    return fp64 ? dispatch_fs2_f64(E, out, a, nb, bs, lds, s) : dispatch_fs2_f32(E, out, a, nb, bs, lds, s);
+}
+
 } // namespace lctk

@@ -33,6 +33,19 @@ struct FrArgs {
     Sched sc;         // radix schedule of the length-2N DFT
 };
 
+struct FsArgs {
+    int N, N1, N2;  // N = N1 N2
+    int C;          // columns per pass-1 work-group
+    int RR;         // rows per pass-2 work-group
+    int T1, T2;     // threads per length-N1 / length-N2 DFT
+    int mode;       // 0 forward, 1 adjoint
+    int64_t batch;
+    const double *M4;
+    LctConst k;
+    NConst nc;
+    Sched sc1, sc2;
+};
+
 // Largest work-group a kernel instantiation accepts (its launch bound): the
 // register budget per thread is 512 / (waves per SIMD) VGPRs, so larger E
 // (more values per thread) gets a smaller bound.
@@ -55,6 +68,16 @@ hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs
                                    hipStream_t s);                                                                   \
     hipError_t dispatch_pgrad_##tag(int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,    \
                                     int bs, size_t lds, hipStream_t s);
+hipError_t launch_fs1(bool fp64, int E, const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds,
+                      hipStream_t s);
+hipError_t launch_fs2(bool fp64, int E, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s);
+#define LCTK_FS_DECL(tag)                                                                                          \
+    hipError_t dispatch_fs1_##tag(int E, const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds,     \
+                                  hipStream_t s);                                                                  \
+    hipError_t dispatch_fs2_##tag(int E, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s);
+LCTK_FS_DECL(f32)
+LCTK_FS_DECL(f64)
+#undef LCTK_FS_DECL
 LCTK_DISPATCH_DECL(f32)
 LCTK_DISPATCH_DECL(f64)
 #undef LCTK_DISPATCH_DECL

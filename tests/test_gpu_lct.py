@@ -253,3 +253,71 @@ def test_error_codes_on_device_buffers():
         lct.frft_exec(p, 1.5, x)
     with pytest.raises(TypeError):
         lct.lct_exec(p, x.to(torch.complex128))
+
+
+# ---------------------------------------------------------------------------
+# Two-pass (four-step) sizes beyond one work-group's LDS.
+# ---------------------------------------------------------------------------
+def peak_rows(M, gp, N, nrow, seed):
+    """Rows where a chirped Gaussian's LCT has its energy (from the Gaussian
+    integral's modulus, used only to choose which rows to compare) plus random rows."""
+    a, b, c, d = M
+    mu, sigma, kappa = gp
+    al = 1 / (2 * sigma ** 2) - 1j * kappa
+    be = -mu / (2 * sigma ** 2)
+    y = oracle.output_nodes(N, b)
+    A = al - 1j * a / (2 * b)
+    B = be + 1j * y / (2 * b)
+    logmag = np.real(B * B / A)
+    top = np.argsort(-logmag)[: nrow // 2]
+    rnd = np.random.default_rng(seed).choice(N, nrow - nrow // 2, replace=False)
+    return np.unique(np.concatenate([top, rnd]))
+
+
+def check_large(N, dtype, batch, nrow, tol, seed=0, adjoint=False):
+    g = np.random.default_rng(500 + N + seed)
+    M = workloads.sl2_params(batch, g)
+    gp = workloads.gaussian_params(batch, g)
+    f = workloads.chirped_gaussians(oracle.nodes(N), gp)
+    x = dev(f, dtype)
+    M4 = dev(M, torch.float64)
+    y = (lct.lct_exec_many_adjoint if adjoint else lct.lct_exec_many)(x, M4)
+    torch.cuda.synchronize()
+    fin = x.cpu().numpy().astype(np.complex128)
+    yh = y.cpu().numpy()
+    for s in range(batch):
+        if adjoint:
+            ref = oracle.lct_adjoint(fin[s], *M[s])  # every output (dense O(N^2))
+            got = yh[s]
+        else:
+            rows = peak_rows(M[s], gp[s], N, nrow, s)
+            ref = oracle.lct(fin[s], *M[s], rows=rows)
+            got = yh[s][rows]
+        e = rel_rows(got, ref)[0]
+        assert e <= tol, (N, s, M[s], e)
+
+
+@pytest.mark.parametrize("N", [32768, 40960, 49152, 65536, 131072])
+def test_two_pass_fp32(N):
+    check_large(N, torch.complex64, 2, 96, 2e-5)
+
+
+@pytest.mark.parametrize("N", [16384, 32768, 61440])
+def test_two_pass_fp64(N):
+    check_large(N, torch.complex128, 2, 64, 1e-12)
+
+
+def test_two_pass_2_20():
+    """16 signals x N = 2^20 (the large-N configuration), 24 sampled outputs each."""
+    check_large(1 << 20, torch.complex64, 16, 24, 2e-5, seed=1)
+
+
+def test_two_pass_adjoint_fp32():
+    check_large(32768, torch.complex64, 1, 16, 2e-5, adjoint=True)
+
+
+def test_two_pass_rejects_in_place():
+    x = torch.zeros(1, 32768, dtype=torch.complex64, device="cuda")
+    M4 = torch.tensor([[1.0, 1.0, 0.0, 1.0]], dtype=torch.float64, device="cuda")
+    with pytest.raises(lct.LctError):
+        lct.lct_exec_many(x, M4, out=x)
