@@ -14,8 +14,9 @@
  * complex64, the FP64 path 16-byte complex128.  A batch is `batch` signals of N
  * samples stored contiguously (signal s occupies elements [s*N, (s+1)*N)).
  * Every `in`, `out`, parameter and workspace pointer is DEVICE memory owned by
- * the caller, unless the comment says host.  `in == out` is allowed (the
- * transform of one signal reads all its input before writing any output).
+ * the caller, unless the comment says host.  `in == out` is allowed for the
+ * single-pass LCT sizes (a signal's input is read before any of its output is
+ * written); the two-pass sizes and the fractional transform need in != out.
  *
  * Execution is asynchronous on `stream` (a hipStream_t; NULL means the
  * default stream).  The library never synchronises and never allocates device
@@ -25,7 +26,8 @@
  *
  * Supported sizes: N = 2^p 3^q 5^r with 1 <= N <= 2^24.  Sizes up to the LDS
  * limit (FP32: 16384 points, FP64: 8192) run as one pass per signal; larger
- * sizes use a two-pass (four-step) FFT through `out`.
+ * sizes use a two-pass (four-step) FFT through `out` (then in != out is
+ * required).
  */
 #ifndef LCT_MI355X_H
 #define LCT_MI355X_H
@@ -129,6 +131,20 @@ int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, i
 /* One order per signal: Z2 is DEVICE memory of batch x 2 doubles (re, im). */
 int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out,
                    int64_t batch, hipStream_t stream);
+
+/*
+ * When 2N exceeds the single-pass limit the convolution runs as two-pass FFTs
+ * through a caller-owned DEVICE workspace (16-byte aligned) of
+ * frft_workspace_size(N, prec, batch) bytes (0 when none is needed):
+ * 3 x 2N complex samples per signal (the data's and the kernel's spectra and
+ * the inverse transform's intermediate).  Without enough workspace the calls
+ * return LCT_ERR_WORKSPACE and do nothing.  in != out is required.
+ */
+size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch);
+int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,
+                 void *ws, size_t ws_bytes, hipStream_t stream);
+int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out,
+                      int64_t batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Host helper: input nodes x (N doubles, eq. asymcer) and output nodes y

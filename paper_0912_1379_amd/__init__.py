@@ -40,6 +40,7 @@ from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODU
 __all__ = [
     "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
     "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
+    "frft_workspace_size",
     "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
     "LCT_FP32", "LCT_FP64",
 ]
@@ -205,25 +206,45 @@ def lct_param_grad_many(f: torch.Tensor, g: torch.Tensor, M4: torch.Tensor, grad
     return grad4
 
 
-def frft_exec(plan: Plan, z: complex, x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+def frft_workspace_size(N: int, precision: int, batch: int) -> int:
+    return int(_lib.load().frft_workspace_size(int(N), int(precision), int(batch)))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def frft_exec(plan: Plan, z: complex, x: torch.Tensor, out=None, stream=None, ws=None) -> torch.Tensor:
+    """Fractional transform with the plan's size and precision.  A workspace is
+    allocated (torch) when the size needs one and `ws` is not given."""
     batch, out = _plan_io(plan, x, out)
     z = complex(z)
-    rc = _lib.load().frft_exec(plan.handle, z.real, z.imag, x.data_ptr(), out.data_ptr(), batch,
-                               _stream_handle(stream))
-    _lib.check(rc, "frft_exec")
+    need = frft_workspace_size(plan.N, plan.precision, batch)
+    if ws is None:
+        ws = _workspace(need, x.device)
+    rc = _lib.load().frft_exec_ws(plan.handle, z.real, z.imag, x.data_ptr(), out.data_ptr(), batch,
+                                  0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
+                                  _stream_handle(stream))
+    _lib.check(rc, "frft_exec_ws")
     return out
 
 
-def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None, ws=None) -> torch.Tensor:
     _check_data(x, "x")
     prec = _prec_of(x)
     N = x.shape[-1]
     batch = _batch_of(x, N)
     _check_params(Z2, batch, 2, "Z2")
     out = _out_like(x, out)
-    rc = _lib.load().frft_exec_many(N, prec, Z2.data_ptr(), x.data_ptr(), out.data_ptr(), batch,
-                                    _stream_handle(stream))
-    _lib.check(rc, "frft_exec_many")
+    need = frft_workspace_size(N, prec, batch)
+    if ws is None:
+        ws = _workspace(need, x.device)
+    rc = _lib.load().frft_exec_many_ws(N, prec, Z2.data_ptr(), x.data_ptr(), out.data_ptr(), batch,
+                                       0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
+                                       _stream_handle(stream))
+    _lib.check(rc, "frft_exec_many_ws")
     return out
 
 

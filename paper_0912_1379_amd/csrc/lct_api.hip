@@ -291,8 +291,50 @@ int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode,
     return hip_status(launch_lct(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
 }
 
+size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
+{
+    if (2 * N <= lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
+        return 0;
+    return (size_t)batch * 3 * (size_t)(2 * N) * (fp64 ? 16 : 8);
+}
+
+int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
+               void *ws, hipStream_t s)
+{
+    FsTiling f = make_fs(2 * N, fp64);
+    if (!f.ok)
+        return LCT_ERR_UNSUPPORTED;
+    FrLArgs a{};
+    a.N = (int)N;
+    a.L = (int)(2 * N);
+    a.L1 = f.N1;
+    a.L2 = f.N2;
+    a.C = f.C;
+    a.RR = f.RR;
+    a.T1 = f.T1;
+    a.T2 = f.T2;
+    a.batch = batch;
+    a.Z2 = Z2;
+    if (k)
+        a.k = *k;
+    a.sc1 = f.sc1;
+    a.sc2 = f.sc2;
+    const int64_t nb1 = batch * (f.N2 / f.C), nb2 = batch * (f.N1 / f.RR);
+    if (2 * nb1 > INT32_MAX || 2 * nb2 > INT32_MAX || batch > INT32_MAX)
+        return LCT_ERR_ARG;
+    hipError_t e;
+    if ((e = launch_frl1(fp64, f.E1, in, ws, a, 0, (int)(2 * nb1), f.bs1, f.lds1, s)) != hipSuccess ||
+        (e = launch_frl2(fp64, f.E2, ws, out, a, 0, (int)(2 * nb2), f.bs2, f.lds2, s)) != hipSuccess ||
+        (e = launch_frl1(fp64, f.E1, in, ws, a, 1, (int)nb1, f.bs1, f.lds1, s)) != hipSuccess ||
+        (e = launch_frl2(fp64, f.E2, ws, out, a, 1, (int)nb2, f.bs2, f.lds2, s)) != hipSuccess)
+        return LCT_ERR_HIP;
+    if (Z2 != nullptr || (k && k->special))
+        return hip_status(launch_fr_special(fp64, in, out, a, s));
+    return LCT_OK;
+}
+
 int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
-             hipStream_t s)
+             void *ws, size_t ws_bytes, hipStream_t s)
 {
     if (batch < 0)
         return LCT_ERR_ARG;
@@ -305,8 +347,12 @@ int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const voi
         return rc;
     if (in == out)
         return LCT_ERR_ARG; // the Hankel form reads the input reversed
-    if (2 * N > lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
-        return LCT_ERR_UNSUPPORTED;
+    if (2 * N > lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32)) {
+        const size_t need = frft_ws_bytes(N, fp64, batch);
+        if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws) % 16)
+            return LCT_ERR_WORKSPACE;
+        return frft_large(N, fp64, Z2, k, in, out, batch, ws, s);
+    }
     Tiling tl = make_tiling(2 * N, fp64, true, 0);
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;
@@ -452,7 +498,27 @@ int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, i
     if (hypot(z_re, z_im) > 1.0 + 1e-12)
         return LCT_ERR_DOMAIN;
     FrConst k = fr_const(p->N, z_re, z_im);
-    return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, stream);
+    return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, nullptr, 0, stream);
+}
+
+int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch, void *ws,
+                 size_t ws_bytes, hipStream_t stream)
+{
+    if (!p)
+        return LCT_ERR_ARG;
+    if (!isfinite(z_re) || !isfinite(z_im))
+        return LCT_ERR_ARG;
+    if (hypot(z_re, z_im) > 1.0 + 1e-12)
+        return LCT_ERR_DOMAIN;
+    FrConst k = fr_const(p->N, z_re, z_im);
+    return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, ws_bytes, stream);
+}
+
+size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch)
+{
+    if (!smooth235(N) || batch < 0 || (prec != LCT_FP32 && prec != LCT_FP64))
+        return 0;
+    return frft_ws_bytes(N, prec == LCT_FP64, batch);
 }
 
 int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out, int64_t batch,
@@ -462,7 +528,17 @@ int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *
         return LCT_ERR_ARG;
     if (batch > 0 && (Z2 == nullptr || ((uintptr_t)Z2) % 8))
         return LCT_ERR_ARG;
-    return frft_run(N, prec == LCT_FP64, Z2, nullptr, in, out, batch, stream);
+    return frft_run(N, prec == LCT_FP64, Z2, nullptr, in, out, batch, nullptr, 0, stream);
+}
+
+int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out, int64_t batch,
+                      void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (prec != LCT_FP32 && prec != LCT_FP64)
+        return LCT_ERR_ARG;
+    if (batch > 0 && (Z2 == nullptr || ((uintptr_t)Z2) % 8))
+        return LCT_ERR_ARG;
+    return frft_run(N, prec == LCT_FP64, Z2, nullptr, in, out, batch, ws, ws_bytes, stream);
 }
 
 int lct_nodes(int64_t N, double b, double d, double *x, double *y)

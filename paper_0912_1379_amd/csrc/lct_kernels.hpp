@@ -68,6 +68,29 @@ hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs
                                    hipStream_t s);                                                                   \
     hipError_t dispatch_pgrad_##tag(int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,    \
                                     int bs, size_t lds, hipStream_t s);
+// Fractional transform beyond one work-group: length L = 2N = L1 L2.
+struct FrLArgs {
+    int N, L, L1, L2;
+    int C, RR, T1, T2;
+    int64_t batch;
+    const double *Z2;
+    FrConst k;
+    Sched sc1, sc2;
+};
+hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs,
+                       size_t lds, hipStream_t s);
+hipError_t launch_frl2(bool fp64, int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,
+                       size_t lds, hipStream_t s);
+hipError_t launch_fr_special(bool fp64, const void *in, void *out, const FrLArgs &a, hipStream_t s);
+#define LCTK_FRL_DECL(tag)                                                                                         \
+    hipError_t dispatch_frl1_##tag(int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs, \
+                                   size_t lds, hipStream_t s);                                                    \
+    hipError_t dispatch_frl2_##tag(int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,      \
+                                   size_t lds, hipStream_t s);                                                    \
+    hipError_t dispatch_fr_special_##tag(const void *in, void *out, const FrLArgs &a, hipStream_t s);
+LCTK_FRL_DECL(f32)
+LCTK_FRL_DECL(f64)
+#undef LCTK_FRL_DECL
 hipError_t launch_fs1(bool fp64, int E, const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds,
                       hipStream_t s);
 hipError_t launch_fs2(bool fp64, int E, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s);

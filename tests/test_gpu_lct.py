@@ -321,3 +321,51 @@ def test_two_pass_rejects_in_place():
     M4 = torch.tensor([[1.0, 1.0, 0.0, 1.0]], dtype=torch.float64, device="cuda")
     with pytest.raises(lct.LctError):
         lct.lct_exec_many(x, M4, out=x)
+
+
+# ---------------------------------------------------------------------------
+# Fractional transform beyond one work-group (length-2N convolution in two
+# passes through a workspace).
+# ---------------------------------------------------------------------------
+def frft_peak_rows(gp, z, N, nrow, seed):
+    """Rows where the continuous transform of the chirped Gaussian has its
+    energy (Gaussian integral's modulus; only used to pick rows) plus random rows."""
+    mu, sigma, kappa = gp
+    al = 1 / (2 * sigma ** 2) - 1j * kappa
+    be = -mu / (2 * sigma ** 2)
+    y = oracle.nodes(N)
+    A = (1 + z * z) / (2 * (1 - z * z)) + al
+    B = y * z / (1 - z * z) - be
+    logmag = np.real(B * B / A - (1 + z * z) * y * y / (2 * (1 - z * z)))
+    top = np.argsort(-logmag)[: nrow // 2]
+    rnd = np.random.default_rng(seed).choice(N, nrow - nrow // 2, replace=False)
+    return np.unique(np.concatenate([top, rnd]))
+
+
+@pytest.mark.parametrize("dtype,tol,N", [(torch.complex64, 2e-5, 16384), (torch.complex64, 2e-5, 24576),
+                                         (torch.complex64, 2e-5, 65536), (torch.complex128, 1e-11, 5120),
+                                         (torch.complex128, 1e-11, 16384)])
+def test_frft_two_pass(dtype, tol, N):
+    zs = [0.6 * np.exp(-1.1j), -0.7 + 0.2j, 0.9 * np.exp(2.5j), 1j, 1.0, -1.0]
+    gen = np.random.default_rng(N)
+    gp = workloads.gaussian_params(len(zs), gen)
+    x = dev(workloads.chirped_gaussians(oracle.nodes(N), gp), dtype)
+    Z2 = dev(np.stack([np.real(zs), np.imag(zs)], axis=1), torch.float64)
+    prec = lct.LCT_FP64 if dtype == torch.complex128 else lct.LCT_FP32
+    assert lct.frft_workspace_size(N, prec, len(zs)) == len(zs) * 3 * 2 * N * (16 if prec else 8)
+    y = lct.frft_exec_many(x, Z2).cpu().numpy()
+    fin = x.cpu().numpy().astype(np.complex128)
+    for s, z in enumerate(zs):
+        rows = frft_peak_rows(gp[s], z, N, 64, s) if abs(z) < 1 or z.imag != 0 else np.arange(0, N, N // 64)
+        ref = oracle.frft(fin[s], z, rows=rows)
+        assert rel_rows(y[s][rows], ref)[0] <= tol, (N, z)
+
+
+def test_frft_two_pass_needs_workspace():
+    N = 16384
+    x = torch.zeros(1, N, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    Z2 = torch.tensor([[0.5, 0.1]], dtype=torch.float64, device="cuda")
+    lib = lct._lib.load()
+    rc = lib.frft_exec_many(N, 0, Z2.data_ptr(), x.data_ptr(), y.data_ptr(), 1, torch.cuda.current_stream().cuda_stream)
+    assert rc == lct.LCT_ERR_WORKSPACE
