@@ -147,6 +147,44 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
                       int64_t batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Ragged batch in one persistent launch: signals of different lengths, each
+ * an LCT with its own matrix or a same-grid fractional transform with its own
+ * order.  This extends the paper's single-transform statement to a batch.
+ *
+ * A descriptor per signal (the same array on the host for planning and on
+ * the device for execution; sizes, kinds and offsets must agree, the
+ * parameters p may change between executions):
+ *   offset  element offset of the signal in `in` and `out` (complex64)
+ *   N       its length (2^p 3^q 5^r, at most 65536 for the fractional
+ *           transform and the LCT alike in this build)
+ *   kind    LCT_KIND_LCT: p = (a, b, c, d), ad - bc = 1;
+ *           LCT_KIND_FRFT: p = (re z, im z, -, -), |z| <= 1
+ * The plan validates the host descriptors, groups short signals of one length
+ * into work items, sorts the items by estimated cost (largest first) and
+ * keeps the item list in plan-owned device memory.  lct_exec_ragged launches
+ * one persistent kernel whose work-groups take items from a counter in the
+ * workspace until none is left; the launch (counter reset + kernel) is
+ * recorded once per (d_desc, in, out, ws) into a HIP graph and replayed.
+ * FP32 only; in != out; the workspace (256-byte aligned, DEVICE) holds the
+ * counter and the spectra of long fractional transforms.
+ */
+enum { LCT_KIND_LCT = 0, LCT_KIND_FRFT = 1 };
+typedef struct {
+    int64_t offset;
+    int32_t N;
+    int32_t kind;
+    double p[4];
+} lct_desc;
+typedef struct lct_ragged_s *lct_ragged_plan;
+int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t nsig, lct_precision prec);
+size_t lct_ragged_workspace_size(lct_ragged_plan p);
+/* Host query: number of work items, persistent grid size, dynamic LDS bytes. */
+int lct_ragged_info(lct_ragged_plan p, int *nitems, int *grid, size_t *lds_bytes);
+int lct_exec_ragged(lct_ragged_plan p, const lct_desc *d_desc, const void *in, void *out, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+void lct_ragged_plan_destroy(lct_ragged_plan p);
+
+/*
  * Host helper: input nodes x (N doubles, eq. asymcer) and output nodes y
  * (N doubles: 4 b x_j / pi, or x_j / d when b == 0).  Either pointer may be NULL.
  * Host memory.  Returns LCT_ERR_ARG for N < 1 or b == d == 0.

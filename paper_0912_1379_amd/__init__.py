@@ -40,7 +40,8 @@ from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODU
 __all__ = [
     "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
     "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
-    "frft_workspace_size",
+    "frft_workspace_size", "RaggedPlan", "make_descriptors", "lct_ragged_plan_create", "lct_exec_ragged",
+    "LCT_KIND_LCT", "LCT_KIND_FRFT",
     "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
     "LCT_FP32", "LCT_FP64",
 ]
@@ -245,6 +246,85 @@ def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None, ws=
                                        0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
                                        _stream_handle(stream))
     _lib.check(rc, "frft_exec_many_ws")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Ragged batches: one persistent launch over signals of different lengths.
+# ---------------------------------------------------------------------------
+DESC_DTYPE = np.dtype([("offset", "<i8"), ("N", "<i4"), ("kind", "<i4"), ("p", "<f8", (4,))])
+LCT_KIND_LCT = 0
+LCT_KIND_FRFT = 1
+
+
+def make_descriptors(sizes, kinds, params) -> np.ndarray:
+    """Descriptor array (C layout lct_desc) for signals stored back to back:
+    sizes[i] samples, kinds[i] in {LCT_KIND_LCT, LCT_KIND_FRFT}, params[i] =
+    (a, b, c, d) or (re z, im z, 0, 0)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    d = np.zeros(sizes.shape[0], dtype=DESC_DTYPE)
+    d["offset"] = np.concatenate([[0], np.cumsum(sizes)[:-1]]) if sizes.size else []
+    d["N"] = sizes
+    d["kind"] = np.asarray(kinds, dtype=np.int32)
+    d["p"] = np.asarray(params, dtype=np.float64).reshape(-1, 4)
+    return d
+
+
+class RaggedPlan:
+    """Owns an ``lct_ragged_plan`` and a device copy of the descriptors."""
+
+    def __init__(self, desc: np.ndarray, precision: int = LCT_FP32, device="cuda"):
+        desc = np.ascontiguousarray(desc, dtype=DESC_DTYPE)
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.lct_ragged_plan_create(ctypes.byref(h), desc.ctypes.data, desc.shape[0], int(precision)),
+                   "lct_ragged_plan_create")
+        self._h = h
+        self.desc = desc
+        self.total = int((desc["offset"] + desc["N"]).max()) if desc.size else 0
+        self.d_desc = torch.from_numpy(desc.view(np.uint8).copy()).to(device)
+        self.ws_bytes = int(lib.lct_ragged_workspace_size(h))
+        ni, gr, ld = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        lib.lct_ragged_info(h, ctypes.byref(ni), ctypes.byref(gr), ctypes.byref(ld))
+        self.items, self.grid, self.lds = ni.value, gr.value, ld.value
+        self.ws = None
+
+    def set_params(self, params) -> None:
+        """New per-signal parameters (same sizes, kinds and offsets)."""
+        self.desc["p"] = np.asarray(params, dtype=np.float64).reshape(-1, 4)
+        self.d_desc.copy_(torch.from_numpy(self.desc.view(np.uint8).copy()))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().lct_ragged_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def lct_ragged_plan_create(desc: np.ndarray, precision: int = LCT_FP32) -> RaggedPlan:
+    return RaggedPlan(desc, precision)
+
+
+def lct_exec_ragged(plan: RaggedPlan, x: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
+    """x: 1-D complex64 tensor holding every signal at its descriptor offset."""
+    _check_data(x, "x")
+    if x.dtype != torch.complex64 or x.dim() != 1 or x.numel() < plan.total:
+        raise ValueError("x must be a 1-D complex64 tensor covering every descriptor")
+    out = _out_like(x, out)
+    if ws is None:
+        if plan.ws is None or plan.ws.numel() < plan.ws_bytes:
+            plan.ws = torch.empty(plan.ws_bytes + 256, dtype=torch.uint8, device=x.device)
+        ws = plan.ws
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    rc = _lib.load().lct_exec_ragged(plan._h, plan.d_desc.data_ptr(), x.data_ptr(), out.data_ptr(), aligned,
+                                     ws.numel() - (aligned - base), _stream_handle(stream))
+    _lib.check(rc, "lct_exec_ragged")
     return out
 
 

@@ -48,6 +48,11 @@ SIGNATURES = {
     "frft_workspace_size": (ctypes.c_size_t, [_i64, _int, _i64]),
     "frft_exec_ws": (_int, [_vp, _d, _d, _vp, _vp, _i64, _vp, ctypes.c_size_t, _vp]),
     "frft_exec_many_ws": (_int, [_i64, _int, _vp, _vp, _vp, _i64, _vp, ctypes.c_size_t, _vp]),
+    "lct_ragged_plan_create": (_int, [ctypes.POINTER(_vp), _vp, _i64, _int]),
+    "lct_ragged_workspace_size": (ctypes.c_size_t, [_vp]),
+    "lct_ragged_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_size_t)]),
+    "lct_exec_ragged": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "lct_ragged_plan_destroy": (None, [_vp]),
     "lct_nodes": (_int, [_i64, _d, _d, _dp, _dp]),
     "lct_strerror": (ctypes.c_char_p, [_int]),
     "lct_max_single_pass": (_i64, [_int]),

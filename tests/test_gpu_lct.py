@@ -369,3 +369,75 @@ def test_frft_two_pass_needs_workspace():
     lib = lct._lib.load()
     rc = lib.frft_exec_many(N, 0, Z2.data_ptr(), x.data_ptr(), y.data_ptr(), 1, torch.cuda.current_stream().cuda_stream)
     assert rc == lct.LCT_ERR_WORKSPACE
+
+
+# ---------------------------------------------------------------------------
+# Ragged batch in one persistent launch.
+# ---------------------------------------------------------------------------
+def ragged_case(count, seed, sizes=None):
+    g = np.random.default_rng(seed)
+    N = workloads.ragged_sizes(count, g) if sizes is None else np.asarray(sizes)
+    kinds = np.where(np.arange(len(N)) % 2 == 0, lct.LCT_KIND_LCT, lct.LCT_KIND_FRFT)
+    M = workloads.sl2_params(len(N), g)
+    z = workloads.frft_orders(len(N), g)
+    gp = workloads.gaussian_params(len(N), g)
+    params = np.where(kinds[:, None] == lct.LCT_KIND_LCT, M,
+                      np.stack([z.real, z.imag, 0 * z.real, 0 * z.real], axis=1))
+    desc = lct.make_descriptors(N, kinds, params)
+    x = np.concatenate([workloads.chirped_gaussians(oracle.nodes(n), gp[i:i + 1])[0] for i, n in enumerate(N)])
+    return N, kinds, M, z, gp, desc, x
+
+
+def check_ragged(N, kinds, M, z, gp, desc, xin, y, which, nrow=48):
+    for i in which:
+        n, off = int(N[i]), int(desc["offset"][i])
+        f = xin[off:off + n]
+        got = y[off:off + n]
+        if kinds[i] == lct.LCT_KIND_LCT:
+            rows = None if n <= 2048 else peak_rows(M[i], gp[i], n, nrow, i)
+            ref = oracle.lct(f, *M[i], rows=rows)
+        else:
+            rows = None if n <= 2048 else frft_peak_rows(gp[i], z[i], n, nrow, i)
+            ref = oracle.frft(f, z[i], rows=rows)
+        if rows is not None:
+            got = got[rows]
+        e = rel_rows(got, ref)[0]
+        assert e <= 2e-5, (i, n, int(kinds[i]), e)
+
+
+def test_ragged_every_size_and_kind():
+    sizes = workloads.smooth_sizes(256, 65536)
+    both = np.repeat(sizes, 2)  # each size once as an LCT and once as a fractional transform
+    N, kinds, M, z, gp, desc, x = ragged_case(len(both), 31, sizes=both)
+    plan = lct.RaggedPlan(desc)
+    xd = dev(x, torch.complex64)
+    y = lct.lct_exec_ragged(plan, xd).cpu().numpy()
+    check_ragged(N, kinds, M, z, gp, desc, xd.cpu().numpy().astype(np.complex128), y, range(len(N)))
+
+
+def test_ragged_repeat_is_deterministic_and_params_update():
+    N, kinds, M, z, gp, desc, x = ragged_case(64, 32)
+    plan = lct.RaggedPlan(desc)
+    xd = dev(x, torch.complex64)
+    y1 = lct.lct_exec_ragged(plan, xd)
+    y2 = lct.lct_exec_ragged(plan, xd, out=torch.empty_like(xd))
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    # new parameters through the device descriptors, same graph
+    M2 = workloads.sl2_params(len(N), np.random.default_rng(5))
+    params = desc["p"].copy()
+    params[kinds == lct.LCT_KIND_LCT] = M2[kinds == lct.LCT_KIND_LCT]
+    plan.set_params(params)
+    y3 = lct.lct_exec_ragged(plan, xd).cpu().numpy()
+    M[kinds == lct.LCT_KIND_LCT] = M2[kinds == lct.LCT_KIND_LCT]
+    check_ragged(N, kinds, M, z, gp, desc, xd.cpu().numpy().astype(np.complex128), y3, range(0, len(N), 5))
+
+
+def test_ragged_full_size_sampled():
+    """10,000 signals (the uneven-batch configuration), 16 of them checked."""
+    N, kinds, M, z, gp, desc, x = ragged_case(10000, 2)
+    plan = lct.RaggedPlan(desc)
+    xd = dev(x, torch.complex64)
+    y = lct.lct_exec_ragged(plan, xd).cpu().numpy()
+    pick = np.random.default_rng(3).choice(len(N), 16, replace=False)
+    check_ragged(N, kinds, M, z, gp, desc, xd.cpu().numpy().astype(np.complex128), y, pick, nrow=24)
