@@ -101,6 +101,141 @@ def cpu_baseline(xh: np.ndarray, M: np.ndarray, yh: np.ndarray, budget_s: float)
     }, errs
 
 
+def bench_ragged(args):
+    """Uneven batch in one persistent launch: 10,000 signals, N log-uniform on
+    [256, 65536] snapped to {2^k, 3 2^k, 5 2^k}, half LCTs (one matrix each),
+    half fractional transforms (one order each), FP32."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    count = args.signals if args.signals != 4096 else 10000
+    g = workloads.rng(2)
+    N = workloads.ragged_sizes(count, g)
+    kinds = np.where(np.arange(count) % 2 == 0, lct.LCT_KIND_LCT, lct.LCT_KIND_FRFT)
+    M = workloads.sl2_params(count, g)
+    z = workloads.frft_orders(count, g)
+    gp = workloads.gaussian_params(count, g)
+    params = np.where(kinds[:, None] == lct.LCT_KIND_LCT, M, np.stack([z.real, z.imag, 0 * z.real, 0 * z.real], 1))
+    desc = lct.make_descriptors(N, kinds, params)
+    parts = []
+    for i, n in enumerate(N):
+        xn, _ = lct.lct_nodes(int(n), 1.0)
+        parts.append(workloads.chirped_gaussians(xn, gp[i:i + 1])[0].astype(np.complex64))
+    x = torch.from_numpy(np.concatenate(parts)).to("cuda")
+    plan = lct.RaggedPlan(desc)
+    y = torch.empty_like(x)
+    ms, ms_kernel, wall = time_launches(lambda: lct.lct_exec_ragged(plan, x, out=y), args.steps, args.warmup)
+    samples = int(N.sum())
+    gbps = 16.0 * samples / (ms_kernel * 1e-3) / 1e9
+    return {
+        "metric": "complex samples/s, ragged batch in one persistent launch",
+        "value": samples / (ms * 1e-3), "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ragged: {count} signals, N in [256, 65536] (2^k, 3 2^k, 5 2^k), half LCT half "
+                               "fractional transform, one persistent launch", "signals": count, "samples": samples,
+                   "items": plan.items, "grid": plan.grid},
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_ragged", "kernel_ms": ms_kernel,
+                     "algorithmic_bytes_per_launch": 16.0 * samples},
+        "wall_s_timed": wall,
+    }
+
+
+def bench_large(args):
+    """16 signals x N = 2^20: FP32 and FP64 two-pass paths, chirped Gaussians
+    plus white complex noise (std 1e-3)."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    B, N = 16, 1 << 20
+    g = workloads.rng(3)
+    M = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    xn, _ = lct.lct_nodes(N, 1.0)
+    f = workloads.chirped_gaussians(xn, gp) + workloads.white_noise((B, N), g)
+    x32 = torch.from_numpy(f).to("cuda").to(torch.complex64)
+    x64 = x32.to(torch.complex128)
+    M4 = torch.from_numpy(M).to("cuda")
+    y32, y64 = torch.empty_like(x32), torch.empty_like(x64)
+    ms, ms_kernel, wall = time_launches(lambda: lct.lct_exec_many(x32, M4, out=y32), args.steps, args.warmup)
+    ms64, ms64_kernel, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64), max(5, args.steps // 2), 2)
+    samples = B * N
+    gbps = 16.0 * samples / (ms_kernel * 1e-3) / 1e9
+    out = {
+        "metric": "complex samples/s, batched LCT N=2^20 (two-pass)",
+        "value": samples / (ms * 1e-3), "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 signals x N=2^20, chirped Gaussians + 1e-3 white noise, one matrix per signal",
+                   "signals": B, "N": N},
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_fs1+k_fs2",
+                     "kernel_ms": ms_kernel, "algorithmic_bytes_per_launch": 16.0 * samples,
+                     "actual_bytes_per_launch_two_pass": 32.0 * samples},
+        "wall_s_timed": wall,
+        "fp64_path": {"ms_per_step": ms64, "kernel_ms": ms64_kernel, "fp32_speedup": ms64 / ms},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        rows = np.sort(np.random.default_rng(4).choice(N, 64, replace=False))
+        errs32, errs64 = [], []
+        t0 = time.perf_counter()
+        for s in range(2):
+            fin = x32[s].cpu().numpy().astype(np.complex128)
+            ref = oracle.lct(fin, *M[s], rows=rows)
+            errs32.append(float(np.linalg.norm(y32[s].cpu().numpy()[rows] - ref) / np.linalg.norm(ref)))
+            ref64 = oracle.lct(x64[s].cpu().numpy(), *M[s], rows=rows)
+            errs64.append(float(np.linalg.norm(y64[s].cpu().numpy()[rows] - ref64) / np.linalg.norm(ref64)))
+        el = time.perf_counter() - t0
+        out["rel_l2_sampled"] = {"fp32_max": max(errs32), "fp64_max": max(errs64), "rows": 64, "signals": 2}
+        out["cpu_baseline"] = {"value": 2 * 2 * 64 / el, "unit": "output samples/s (dense rows of 2^20 terms)",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"2 signals x 64 rows, FP32 and FP64 inputs, {el:.1f} s"}
+    return out
+
+
+def bench_fit(args):
+    """Differentiable LCT fit: 256 signals x N = 2048 complex64, loss
+    ||abs(LCT_M(f))^2 - I_target||^2 with I_target from a hidden matrix; one
+    step = forward + backward (input and parameter gradients)."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    B, N = 256, 2048
+    g = workloads.rng(4)
+    Mstar = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    xn, _ = lct.lct_nodes(N, 1.0)
+    f = torch.from_numpy(workloads.chirped_gaussians(xn, gp)).to("cuda").to(torch.complex64)
+    with torch.no_grad():
+        target = lct.lct(f, torch.from_numpy(Mstar).to("cuda")).abs() ** 2
+    M0 = Mstar + 0.01 * g.standard_normal(Mstar.shape)
+    M0[:, 2] = (M0[:, 0] * M0[:, 3] - 1) / M0[:, 1]
+    Mp = torch.from_numpy(M0).to("cuda").requires_grad_(True)
+    fp = f.clone().requires_grad_(True)
+
+    def step():
+        y = lct.lct(fp, Mp)
+        loss = ((y.abs() ** 2 - target) ** 2).sum()
+        loss.backward()
+
+    ms, ms_kernel, wall = time_launches(step, args.steps, args.warmup)
+    return {
+        "metric": "steps/s, differentiable LCT fit (forward + backward)",
+        "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fit: 256 signals x N=2048, intensity loss, grads w.r.t. f and (a,b,c,d)",
+                   "signals": B, "N": N},
+        "roofline": None, "wall_s_timed": wall,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +246,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit"], default="batched",
+                    help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
+                         "large: 16 x 2^20; fit: autograd step at 256 x 2048")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,6 +256,11 @@ def main():
               "(signals are independent: a multi-GPU run would shard the batch with no communication)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "batched":
+        fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     import torch
     import paper_0912_1379_amd as lct

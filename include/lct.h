@@ -136,9 +136,10 @@ int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *
  * When 2N exceeds the single-pass limit the convolution runs as two-pass FFTs
  * through a caller-owned DEVICE workspace (16-byte aligned) of
  * frft_workspace_size(N, prec, batch) bytes (0 when none is needed):
- * 3 x 2N complex samples per signal (the data's and the kernel's spectra and
- * the inverse transform's intermediate).  Without enough workspace the calls
- * return LCT_ERR_WORKSPACE and do nothing.  in != out is required.
+ * 2 x 2N complex samples per signal (the data's and the kernel's spectra; the
+ * first also holds the inverse transform's intermediate).  Without enough
+ * workspace the calls return LCT_ERR_WORKSPACE and do nothing.  in != out is
+ * required.
  */
 size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch);
 int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,

@@ -3,18 +3,17 @@
 //
 // g = C D IDFT(DFT(v) . DFT(t)) restricted to the first N outputs, with
 // v = D f zero-padded (reversed for the Hankel form) and t the Gaussian-chirp
-// Toeplitz kernel.  Each length-L DFT is a four-step FFT (L = L1 L2) in two
-// passes; the workspace holds three length-L regions per signal:
-//   R0: DFT(v)  (pass 1 writes it transposed, pass 2 turns it into natural order in place)
-//   R1: DFT(t)  (same)
-//   R2: the inverse transform's transposed intermediate
-// Launches: [pass 1 of v and t] [pass 2 of v and t] [pass 1 of conj(V K)] [pass 2 -> out].
+// Toeplitz kernel.  The length-L DFTs are four-step FFTs (L = L1 L2); the
+// workspace holds two length-L regions per signal (R0 for v, R1 for t).
+// Launches: [pass 1: column DFTs of v and t, twiddled, stored transposed]
+// [pass 2: row DFTs of both, their product and the inverse transform's row
+// step, in place in R0] [pass 3: the inverse's column DFTs -> out].
 #pragma once
 #include "fourstep_impl.hpp"
 
 namespace lctk {
 
-enum FrKind { FR_DATA = 0, FR_KERN = 1, FR_INV = 2 };
+enum FrKind { FR_DATA = 0, FR_KERN = 1 };
 
 template <typename R>
 __device__ __forceinline__ FrConst fr_const_of(const FrLArgs &a, int64_t s)
@@ -23,11 +22,11 @@ __device__ __forceinline__ FrConst fr_const_of(const FrLArgs &a, int64_t s)
 }
 
 // Pass 1 over columns n2 of the length-L sequence (element i = n1 L2 + n2).
-// blockIdx.x < batch * tiles handles the data (FR_DATA, or FR_INV when
-// `inverse`), the rest the kernel sequence (FR_KERN).
+// blockIdx.x < batch * tiles handles the data (FR_DATA), the rest the
+// kernel sequence (FR_KERN).
 template <typename R, int E>
 __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
-    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ ws, FrLArgs a, int inverse)
+    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -35,8 +34,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
     const int N = a.N, L = a.L, L1 = a.L1, L2 = a.L2, Cc = a.C, T1 = a.T1;
     const int tiles = L2 / Cc;
     int64_t b = blockIdx.x;
-    int kind = inverse ? FR_INV : FR_DATA;
-    if (!inverse && b >= a.batch * tiles) {
+    int kind = FR_DATA;
+    if (b >= a.batch * tiles) {
         kind = FR_KERN;
         b -= a.batch * tiles;
     }
@@ -47,9 +46,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
     const int t = tid / Cc;
     const int n2 = n20 + sl;
     const FrConst k = fr_const_of<R>(a, s);
-    V *R0 = ws + (size_t)s * 3 * L;
+    V *R0 = ws + (size_t)s * 2 * L;
     V *R1 = R0 + L;
-    V *R2 = R1 + L;
 
     C<R> v[E];
 #pragma unroll
@@ -61,11 +59,9 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
                 x = ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i));
                 x = cmul(x, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(i, N)));
             }
-        } else if (kind == FR_KERN) {
+        } else {
             const int m = i <= N ? i : L - i;
             x = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, (double)m * (double)m);
-        } else {
-            x = cconj(cmul(ldc<R>(R0 + i), ldc<R>(R1 + i)));
         }
         v[e] = x;
     }
@@ -89,63 +85,105 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
     const int sl2 = tid / T1;
     const int t2 = tid - sl2 * T1;
     const C<R> *l2 = smem + (size_t)sl2 * lds_elems(L1);
-    V *dst = kind == FR_DATA ? R0 : (kind == FR_KERN ? R1 : R2);
+    V *dst = kind == FR_DATA ? R0 : R1;
 #pragma unroll
     for (int e = 0; e < E; ++e)
         stc<R>(dst + (size_t)(n20 + sl2) * L1 + t2 + T1 * e, l2[lds_pad(t2 + T1 * e)]);
 }
 
-// Pass 2 over rows k1 (element n2 of row k1 at n2 L1 + k1).  Forward
-// (inverse == 0): regions R0 and R1 in place, blocks beyond batch * tiles
-// take R1.  Inverse: reads R2 and writes the first N outputs to `out`.
+// Pass 2 over rows k1 (element n2 of row k1 at n2 L1 + k1): the length-L2
+// DFTs of both regions finish the spectra V and K at k = k1 + L1 k2; the
+// inverse transform of P = V K then starts in LDS.  With n = n2 + L2 n1,
+//   sum_k P_k W_L^(-n k) = sum_k1 W_L1^(-n1 k1) [W_L^(-n2 k1) sum_k2 W_L2^(-n2 k2) P_(k1 + L1 k2)],
+// and the conjugate of the bracket (the forward length-L2 DFT of conj(P),
+// times W_L^(+n2 k1), W_L = e^(-2 pi i / L)) is stored into R0 at n2 L1 + k1.
 template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(
-    typename Vec<R>::T *__restrict__ ws, typename Vec<R>::T *__restrict__ out, FrLArgs a, int inverse)
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
-    const int N = a.N, L = a.L, L1 = a.L1, RR = a.RR, T2 = a.T2;
+    const int L = a.L, L1 = a.L1, RR = a.RR, T2 = a.T2;
     const int tiles = L1 / RR;
-    int64_t b = blockIdx.x;
-    int region = inverse ? 2 : 0;
-    if (!inverse && b >= a.batch * tiles) {
-        region = 1;
-        b -= a.batch * tiles;
-    }
+    const int64_t b = blockIdx.x;
     const int64_t s = b / tiles;
     const int k10 = (int)(b - s * tiles) * RR;
     const int tid = (int)threadIdx.x;
     const int r = tid % RR;
     const int t = tid / RR;
     const int k1 = k10 + r;
-    V *reg = ws + (size_t)s * 3 * L + (size_t)region * L;
+    V *R0 = ws + (size_t)s * 2 * L;
+    const V *R1 = R0 + L;
+
+    C<R> v[E], w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const size_t i = (size_t)(t + T2 * e) * L1 + k1;
+        v[e] = ldc<R>(R0 + i);
+        w[e] = ldc<R>(R1 + i);
+    }
+    C<R> *lds = smem + (size_t)r * lds_elems(a.L2);
+    fft_lds<E>(v, lds, t, T2, a.sc2);
+    fft_lds<E>(w, lds, t, T2, a.sc2);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = cconj(cmul(v[e], w[e]));
+    fft_lds<E>(v, lds, t, T2, a.sc2);
+    const double A = -(double)(((int64_t)k1 * t) % L) / (double)L;
+    const double B = -(double)(((int64_t)k1 * T2) % L) / (double)L;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        stc<R>(R0 + (size_t)(t + T2 * e) * L1 + k1, cmul(v[e], cis_turns_from<R>(frac_turns(fma(B, (double)e, A)))));
+}
+
+// Pass 3 over columns n2: the length-L1 DFT over k1 of the contiguous
+// R0[n2 L1 + k1] gives the conjugate of the inverse transform at
+// j = n2 + L2 n1; transposed through LDS (consecutive threads, consecutive j)
+// it is conjugated, multiplied by the diagonal and the constant, and the
+// first N outputs are stored.
+template <typename R, int E>
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl3(const typename Vec<R>::T *__restrict__ ws,
+                                                                       typename Vec<R>::T *__restrict__ out, FrLArgs a)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    const int N = a.N, L = a.L, L1 = a.L1, L2 = a.L2, Cc = a.C, T1 = a.T1;
+    const int tiles = L2 / Cc;
+    const int64_t b = blockIdx.x;
+    const int64_t s = b / tiles;
+    const int n20 = (int)(b - s * tiles) * Cc;
+    const FrConst k = fr_const_of<R>(a, s);
+    if (k.special)
+        return; // whole work-group: k_fr_special writes this signal
+    const int tid = (int)threadIdx.x;
+    const int sl = tid / T1;
+    const int t = tid - sl * T1;
+    const V *R0 = ws + (size_t)s * 2 * L;
 
     C<R> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        v[e] = ldc<R>(reg + (size_t)(t + T2 * e) * L1 + k1);
-
-    C<R> *lds = smem + (size_t)r * lds_elems(a.L2);
-    fft_lds<E>(v, lds, t, T2, a.sc2);
-
-    if (!inverse) {
+        v[e] = ldc<R>(R0 + (size_t)(n20 + sl) * L1 + t + T1 * e);
+    C<R> *lds = smem + (size_t)sl * lds_elems(L1);
+    fft_lds<E>(v, lds, t, T1, a.sc1);
+    __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            stc<R>(reg + (size_t)(t + T2 * e) * L1 + k1, v[e]);
-    } else {
-        const FrConst k = fr_const_of<R>(a, s);
-        if (k.special)
-            return;
+    for (int e = 0; e < E; ++e)
+        lds[lds_pad(t + T1 * e)] = v[e];
+    __syncthreads();
+    const int sl2 = tid % Cc;
+    const int t2 = tid / Cc;
+    const C<R> *l2 = smem + (size_t)sl2 * lds_elems(L1);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int j = k1 + L1 * (t + T2 * e);
-            if (j < N) {
-                C<R> y = cconj(v[e]);
-                y = cmul(y, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
-                y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
-                stc<R>(out + (size_t)s * N + j, y);
-            }
+    for (int e = 0; e < E; ++e) {
+        const int n1 = t2 + T1 * e;
+        const int j = n20 + sl2 + L2 * n1;
+        if (j < N) {
+            C<R> y = cconj(l2[lds_pad(n1)]);
+            y = cmul(y, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
+            y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
+            stc<R>(out + (size_t)s * N + j, y);
         }
     }
 }
@@ -167,8 +205,7 @@ __global__ void k_fr_special(const typename Vec<R>::T *__restrict__ in, typename
 }
 
 template <typename R, int E>
-inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs, size_t lds,
-                                hipStream_t st)
+inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl1<R, E>;
@@ -177,13 +214,12 @@ inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int 
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)in, (V *)ws, a, inverse);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)in, (V *)ws, a);
     return hipGetLastError();
 }
 
 template <typename R, int E>
-inline hipError_t launch_frl2_t(void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs, size_t lds,
-                                hipStream_t st)
+inline hipError_t launch_frl2_t(void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl2<R, E>;
@@ -192,7 +228,22 @@ inline hipError_t launch_frl2_t(void *ws, void *out, const FrLArgs &a, int inver
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (V *)ws, (V *)out, a, inverse);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (V *)ws, a);
+    return hipGetLastError();
+}
+
+template <typename R, int E>
+inline hipError_t launch_frl3_t(const void *ws, void *out, const FrLArgs &a, int nb, int bs, size_t lds,
+                                hipStream_t st)
+{
+    using V = typename Vec<R>::T;
+    auto kern = k_frl3<R, E>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)ws, (V *)out, a);
     return hipGetLastError();
 }
 

@@ -3,13 +3,13 @@
 
 namespace lctk {
 
-hipError_t dispatch_frl1_f32(int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs,
-                               size_t lds, hipStream_t s)
+hipError_t dispatch_frl1_f32(int E, const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds,
+                               hipStream_t s)
 {
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \
-        return launch_frl1_t<float, e>(in, ws, a, inverse, nb, bs, lds, s);
+        return launch_frl1_t<float, e>(in, ws, a, nb, bs, lds, s);
         LCT_E_LIST(X)
 #undef X
     default:
@@ -17,13 +17,26 @@ hipError_t dispatch_frl1_f32(int E, const void *in, void *ws, const FrLArgs &a, 
     }
 }
 
-hipError_t dispatch_frl2_f32(int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,
-                               size_t lds, hipStream_t s)
+hipError_t dispatch_frl2_f32(int E, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \
-        return launch_frl2_t<float, e>(ws, out, a, inverse, nb, bs, lds, s);
+        return launch_frl2_t<float, e>(ws, a, nb, bs, lds, s);
+        LCT_E_LIST(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t dispatch_frl3_f32(int E, const void *ws, void *out, const FrLArgs &a, int nb, int bs, size_t lds,
+                               hipStream_t s)
+{
+    switch (E) {
+#define X(e)                                                                                                         \
+    case e:                                                                                                          \
+        return launch_frl3_t<float, e>(ws, out, a, nb, bs, lds, s);
         LCT_E_LIST(X)
 #undef X
     default:

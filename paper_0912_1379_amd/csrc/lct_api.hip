@@ -295,7 +295,7 @@ size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
 {
     if (2 * N <= lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
         return 0;
-    return (size_t)batch * 3 * (size_t)(2 * N) * (fp64 ? 16 : 8);
+    return (size_t)batch * 2 * (size_t)(2 * N) * (fp64 ? 16 : 8);
 }
 
 int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
@@ -323,10 +323,9 @@ int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const v
     if (2 * nb1 > INT32_MAX || 2 * nb2 > INT32_MAX || batch > INT32_MAX)
         return LCT_ERR_ARG;
     hipError_t e;
-    if ((e = launch_frl1(fp64, f.E1, in, ws, a, 0, (int)(2 * nb1), f.bs1, f.lds1, s)) != hipSuccess ||
-        (e = launch_frl2(fp64, f.E2, ws, out, a, 0, (int)(2 * nb2), f.bs2, f.lds2, s)) != hipSuccess ||
-        (e = launch_frl1(fp64, f.E1, in, ws, a, 1, (int)nb1, f.bs1, f.lds1, s)) != hipSuccess ||
-        (e = launch_frl2(fp64, f.E2, ws, out, a, 1, (int)nb2, f.bs2, f.lds2, s)) != hipSuccess)
+    if ((e = launch_frl1(fp64, f.E1, in, ws, a, (int)(2 * nb1), f.bs1, f.lds1, s)) != hipSuccess ||
+        (e = launch_frl2(fp64, f.E2, ws, a, (int)nb2, f.bs2, f.lds2, s)) != hipSuccess ||
+        (e = launch_frl3(fp64, f.E1, ws, out, a, (int)nb1, f.bs1, f.lds1, s)) != hipSuccess)
         return LCT_ERR_HIP;
     if (Z2 != nullptr || (k && k->special))
         return hip_status(launch_fr_special(fp64, in, out, a, s));

@@ -34,18 +34,21 @@ hipError_t launch_fs2(bool fp64, int E, void *out, const FsArgs &a, int nb, int 
     return fp64 ? dispatch_fs2_f64(E, out, a, nb, bs, lds, s) : dispatch_fs2_f32(E, out, a, nb, bs, lds, s);
 }
 
-hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs,
-                       size_t lds, hipStream_t s)
+hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds,
+                       hipStream_t s)
 {
-    return fp64 ? dispatch_frl1_f64(E, in, ws, a, inverse, nb, bs, lds, s)
-                : dispatch_frl1_f32(E, in, ws, a, inverse, nb, bs, lds, s);
+    return fp64 ? dispatch_frl1_f64(E, in, ws, a, nb, bs, lds, s) : dispatch_frl1_f32(E, in, ws, a, nb, bs, lds, s);
 }
 
-hipError_t launch_frl2(bool fp64, int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,
-                       size_t lds, hipStream_t s)
+hipError_t launch_frl2(bool fp64, int E, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    return fp64 ? dispatch_frl2_f64(E, ws, out, a, inverse, nb, bs, lds, s)
-                : dispatch_frl2_f32(E, ws, out, a, inverse, nb, bs, lds, s);
+    return fp64 ? dispatch_frl2_f64(E, ws, a, nb, bs, lds, s) : dispatch_frl2_f32(E, ws, a, nb, bs, lds, s);
+}
+
+hipError_t launch_frl3(bool fp64, int E, const void *ws, void *out, const FrLArgs &a, int nb, int bs, size_t lds,
+                       hipStream_t s)
+{
+    return fp64 ? dispatch_frl3_f64(E, ws, out, a, nb, bs, lds, s) : dispatch_frl3_f32(E, ws, out, a, nb, bs, lds, s);
 }
 
 hipError_t launch_fr_special(bool fp64, const void *in, void *out, const FrLArgs &a, hipStream_t s)

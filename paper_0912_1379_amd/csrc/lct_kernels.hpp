@@ -77,16 +77,18 @@ struct FrLArgs {
     FrConst k;
     Sched sc1, sc2;
 };
-hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs,
-                       size_t lds, hipStream_t s);
-hipError_t launch_frl2(bool fp64, int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,
-                       size_t lds, hipStream_t s);
+hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds,
+                       hipStream_t s);
+hipError_t launch_frl2(bool fp64, int E, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t s);
+hipError_t launch_frl3(bool fp64, int E, const void *ws, void *out, const FrLArgs &a, int nb, int bs, size_t lds,
+                       hipStream_t s);
 hipError_t launch_fr_special(bool fp64, const void *in, void *out, const FrLArgs &a, hipStream_t s);
 #define LCTK_FRL_DECL(tag)                                                                                         \
-    hipError_t dispatch_frl1_##tag(int E, const void *in, void *ws, const FrLArgs &a, int inverse, int nb, int bs, \
-                                   size_t lds, hipStream_t s);                                                    \
-    hipError_t dispatch_frl2_##tag(int E, void *ws, void *out, const FrLArgs &a, int inverse, int nb, int bs,      \
-                                   size_t lds, hipStream_t s);                                                    \
+    hipError_t dispatch_frl1_##tag(int E, const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds,  \
+                                   hipStream_t s);                                                                \
+    hipError_t dispatch_frl2_##tag(int E, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t s);  \
+    hipError_t dispatch_frl3_##tag(int E, const void *ws, void *out, const FrLArgs &a, int nb, int bs, size_t lds, \
+                                   hipStream_t s);                                                                \
     hipError_t dispatch_fr_special_##tag(const void *in, void *out, const FrLArgs &a, hipStream_t s);
 LCTK_FRL_DECL(f32)
 LCTK_FRL_DECL(f64)

@@ -257,7 +257,7 @@ int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t
                                             : (group ? RI_FRFT_GROUP : RI_FRFT_BIG);
         if (kind_of[s] == RI_FRFT_BIG) {
             wsoff[s] = ws_elems;
-            ws_elems += 3 * 2 * (int64_t)d.N;
+            ws_elems += 2 * 2 * (int64_t)d.N;
         }
     }
 

@@ -13,8 +13,11 @@
 //   RI_LCT_BIG     one signal, four-step inside the work-group: column tiles
 //                  (pre-chirp, DFT, twiddle, transposed store to out), then
 //                  row tiles (DFT, post-chirp, store in place)
-//   RI_FRFT_BIG    one signal, the length-2N convolution as three four-step
-//                  DFTs through the signal's workspace region
+//   RI_FRFT_BIG    one signal, the length-2N convolution through the
+//                  signal's workspace region (two spectra): column passes of
+//                  the data and of the kernel, one row pass that finishes both
+//                  spectra, multiplies them and starts the inverse transform,
+//                  and a closing column pass that writes the outputs
 #pragma once
 #include "frft_large_impl.hpp"
 
@@ -234,6 +237,87 @@ __device__ __forceinline__ void rag_rows(const RagSize &z, CF *smem, const float
     __syncthreads();
 }
 
+// Convolution row pass of the fractional transform: for every tile of RR
+// rows k1, the length-N2 DFTs over n2 of the data (R0[n2 N1 + k1]) and of
+// the kernel (R1[n2 N1 + k1]) complete both spectra at k = k1 + N1 k2.  The
+// inverse transform of their product P starts at once, in LDS: with
+// n = n2 + N2 n1 it splits as
+//   sum_k P_k W_M^(-n k) = sum_k1 W_N1^(-n1 k1) [W_M^(-n2 k1) sum_k2 W_N2^(-n2 k2) P_(k1 + N1 k2)],
+// and the bracket's conjugate, i.e. the forward length-N2 DFT of conj(P)
+// times W_M^(+n2 k1) (W_M = e^(-2 pi i / M)), is stored in place at n2 N1 + k1.
+template <int E2>
+__device__ __forceinline__ void rag_rows_conv(const RagSize &z, int M, CF *smem, float2 *R0, const float2 *R1)
+{
+    const int N1 = z.N1, RR = z.RR, T2 = z.T2;
+    const int tid = (int)threadIdx.x;
+    const int r = tid % RR, t = tid / RR;
+    CF *lds = smem + (size_t)r * lds_elems(z.N2);
+    for (int k10 = 0; k10 < N1; k10 += RR) {
+        const int k1 = k10 + r;
+        const bool rowok = k1 < N1;
+        CF v[E2], w[E2];
+#pragma unroll
+        for (int e = 0; e < E2; ++e) {
+            const size_t i = (size_t)(t + T2 * e) * N1 + k1;
+            v[e] = rowok ? ldc<float>(R0 + i) : CF{0.f, 0.f};
+            w[e] = rowok ? ldc<float>(R1 + i) : CF{0.f, 0.f};
+        }
+        fft_lds<E2>(v, lds, t, T2, z.sc2);
+        fft_lds<E2>(w, lds, t, T2, z.sc2);
+#pragma unroll
+        for (int e = 0; e < E2; ++e)
+            v[e] = cconj(cmul(v[e], w[e]));
+        fft_lds<E2>(v, lds, t, T2, z.sc2);
+        // position n2 = t + T2 e: the inverse's twiddle W_M^(-n2 k1), applied to
+        // the conjugate as W_M^(+n2 k1) = e^(-2 pi i n2 k1 / M)
+        const double A = -(double)(((int64_t)k1 * t) % M) / (double)M;
+        const double B = -(double)(((int64_t)k1 * T2) % M) / (double)M;
+        if (rowok) {
+#pragma unroll
+            for (int e = 0; e < E2; ++e)
+                stc<float>(R0 + (size_t)(t + T2 * e) * N1 + k1,
+                           cmul(v[e], cis_turns_from<float>(frac_turns(fma(B, (double)e, A)))));
+        }
+    }
+    __syncthreads();
+}
+
+// Closing column pass of the inverse transform: for every tile of C
+// columns n2, the length-N1 DFT over k1 of the contiguous src[n2 N1 + k1];
+// the result at n1 belongs to output index j = n2 + N2 n1 and is handed,
+// transposed through LDS so that consecutive threads own consecutive j, to
+// `store(j, value)`.
+template <int E1, class Store>
+__device__ __forceinline__ void rag_icols(const RagSize &z, CF *smem, const float2 *src, Store store)
+{
+    const int N1 = z.N1, N2 = z.N2, Cc = z.C, T1 = z.T1;
+    const int tid = (int)threadIdx.x;
+    const int sl = tid / T1, t = tid - sl * T1;
+    const int sl2 = tid % Cc, t2 = tid / Cc;
+    CF *lds = smem + (size_t)sl * lds_elems(N1);
+    const CF *l2 = smem + (size_t)sl2 * lds_elems(N1);
+    for (int n20 = 0; n20 < N2; n20 += Cc) {
+        const int n2 = n20 + sl;
+        const bool colok = n2 < N2;
+        CF v[E1];
+#pragma unroll
+        for (int e = 0; e < E1; ++e)
+            v[e] = colok ? ldc<float>(src + (size_t)n2 * N1 + t + T1 * e) : CF{0.f, 0.f};
+        fft_lds<E1>(v, lds, t, T1, z.sc1);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E1; ++e)
+            lds[lds_pad(t + T1 * e)] = v[e];
+        __syncthreads();
+        if (n20 + sl2 < N2) {
+#pragma unroll
+            for (int e = 0; e < E1; ++e)
+                store(n20 + sl2 + N2 * (t2 + T1 * e), l2[lds_pad(t2 + T1 * e)]);
+        }
+    }
+    __syncthreads();
+}
+
 // Functors of the column / row passes.
 struct PreChirpLoad { // pre-chirped input samples
     const float2 *src;
@@ -285,25 +369,12 @@ struct GaussKernel { // Toeplitz kernel at circular position i
         return gauss_chirp<float>(kmag, kph_hi, kph_lo, (double)m * (double)m);
     }
 };
-struct SpectrumProduct { // conj(V K), the input of the inverse transform
-    const float2 *V, *K;
-    __device__ void begin(int, int) {}
-    __device__ CF operator()(int i, int) const { return cconj(cmul(ldc<float>(V + i), ldc<float>(K + i))); }
-};
-struct PlainStore { // natural-order spectrum, in place
-    float2 *dst;
-    int N1;
-    __device__ void begin(int, int) {}
-    __device__ void operator()(int k1, int k2, CF y, int) const { stc<float>(dst + (size_t)k2 * N1 + k1, y); }
-};
-struct FrOutStore { // first N outputs of the inverse transform, times the diagonal and constant
+struct FrOutStore { // the first N outputs: conjugate, diagonal e^{-P x_j^2}, constant
     float2 *dst;
     double dmag, dph_hi, dph_lo, cre, cim;
-    int N, N1;
-    __device__ void begin(int, int) {}
-    __device__ void operator()(int k1, int k2, CF y, int) const
+    int N;
+    __device__ void operator()(int j, CF y) const
     {
-        const int j = k1 + N1 * k2;
         if (j < N) {
             CF o = cmul(cconj(y), gauss_chirp<float>(dmag, dph_hi, dph_lo, nsq(j, N)));
             stc<float>(dst + j, cmul(o, CF{(float)cre, (float)cim}));
@@ -340,12 +411,11 @@ __device__ __noinline__ void rag_frft_big(const RagArgs &a, const RagItem &it, c
 {
     const int s = a.sig[it.first];
     const RagDesc d = a.desc[s];
-    const int N = z.N, L = 2 * N, N1 = z.N1;
+    const int N = z.N, L = 2 * N;
     const float2 *src = a.in + d.offset;
     float2 *dst = a.out + d.offset;
     float2 *R0 = a.ws + a.wsoff[s];
     float2 *R1 = R0 + L;
-    float2 *R2 = R1 + L;
     const FrConst k = fr_const(N, d.p[0], d.p[1]);
     if (k.special) {
         for (int j = (int)threadIdx.x; j < N; j += RAG_THREADS)
@@ -355,10 +425,8 @@ __device__ __noinline__ void rag_frft_big(const RagArgs &a, const RagItem &it, c
     }
     rag_cols<E1>(z, L, smem, R0, GaussData{src, k, N});
     rag_cols<E1>(z, L, smem, R1, GaussKernel{k.kmag, k.kph_hi, k.kph_lo, N, L});
-    rag_rows<E2>(z, smem, R0, PlainStore{R0, N1});
-    rag_rows<E2>(z, smem, R1, PlainStore{R1, N1});
-    rag_cols<E1>(z, L, smem, R2, SpectrumProduct{R0, R1});
-    rag_rows<E2>(z, smem, R2, FrOutStore{dst, k.dmag, k.dph_hi, k.dph_lo, k.cre, k.cim, N, N1});
+    rag_rows_conv<E2>(z, L, smem, R0, R1);
+    rag_icols<E1>(z, smem, R0, FrOutStore{dst, k.dmag, k.dph_hi, k.dph_lo, k.cre, k.cim, N});
 }
 
 #define RAG_E_LIST(X) X(16) X(20) X(24)

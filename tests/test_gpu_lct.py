@@ -352,7 +352,7 @@ def test_frft_two_pass(dtype, tol, N):
     x = dev(workloads.chirped_gaussians(oracle.nodes(N), gp), dtype)
     Z2 = dev(np.stack([np.real(zs), np.imag(zs)], axis=1), torch.float64)
     prec = lct.LCT_FP64 if dtype == torch.complex128 else lct.LCT_FP32
-    assert lct.frft_workspace_size(N, prec, len(zs)) == len(zs) * 3 * 2 * N * (16 if prec else 8)
+    assert lct.frft_workspace_size(N, prec, len(zs)) == len(zs) * 2 * 2 * N * (16 if prec else 8)
     y = lct.frft_exec_many(x, Z2).cpu().numpy()
     fin = x.cpu().numpy().astype(np.complex128)
     for s, z in enumerate(zs):
@@ -413,6 +413,26 @@ def test_ragged_every_size_and_kind():
     xd = dev(x, torch.complex64)
     y = lct.lct_exec_ragged(plan, xd).cpu().numpy()
     check_ragged(N, kinds, M, z, gp, desc, xd.cpu().numpy().astype(np.complex128), y, range(len(N)))
+
+
+def test_ragged_special_rows():
+    """b = 0 rows and z = +-1 orders, short and long, inside one ragged launch."""
+    N = np.array([1024, 32768, 2048, 40960, 512, 65536])
+    kinds = np.array([0, 0, 1, 1, 1, 1])
+    params = np.array([[2.0, 0.0, 0.7, 0.5], [-0.5, 0.0, 1.2, -2.0], [1.0, 0, 0, 0], [-1.0, 0, 0, 0],
+                       [-1.0, 0, 0, 0], [1.0, 0, 0, 0]])
+    desc = lct.make_descriptors(N, kinds, params)
+    gp = workloads.gaussian_params(len(N), np.random.default_rng(8))
+    x = np.concatenate([workloads.chirped_gaussians(oracle.nodes(n), gp[i:i + 1])[0] for i, n in enumerate(N)])
+    plan = lct.RaggedPlan(desc)
+    xd = dev(x, torch.complex64)
+    y = lct.lct_exec_ragged(plan, xd).cpu().numpy()
+    xh = xd.cpu().numpy().astype(np.complex128)
+    for i, n in enumerate(N):
+        off = int(desc["offset"][i])
+        f = xh[off:off + n]
+        ref = oracle.lct(f, *params[i]) if kinds[i] == 0 else oracle.frft(f, complex(params[i][0], params[i][1]))
+        assert rel_rows(y[off:off + n], ref)[0] <= 2e-5, i
 
 
 def test_ragged_repeat_is_deterministic_and_params_update():
