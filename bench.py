@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the built-in geometry heuristic instead of autotuning first")
     ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit"], default="batched",
                     help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
                          "large: 16 x 2^20; fit: autograd step at 256 x 2048")
@@ -273,6 +275,15 @@ def main():
     M4 = torch.from_numpy(M).to(dev)
     y32 = torch.empty_like(x32)
 
+    tuning = None
+    if not args.no_tune:
+        # launch geometry picked by the library's autotuner on this device
+        tuning = {"fp32": lct.lct_autotune(N, lct.LCT_FP32, "lct", batch=B)}
+        if not args.no_fp64:
+            tuning["fp64"] = lct.lct_autotune(N, lct.LCT_FP64, "lct", batch=B)
+        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
+    geometry = lct.lct_tune_get(N, lct.LCT_FP32, "lct")
+
     def step32():
         lct.lct_exec_many(x32, M4, out=y32)
 
@@ -299,7 +310,8 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("kernel_hash") == kernel_hash() and rec.get("signals") == B and rec.get("N") == N:
+        if (rec.get("kernel_hash") == kernel_hash() and rec.get("signals") == B and rec.get("N") == N
+                and rec.get("geometry") == geometry):
             traffic = rec.get("bytes_per_launch")
 
     out = {
@@ -317,13 +329,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched LCT, {B} signals x N={N} complex64, one (a,b,c,d) per signal, "
                                "chirped-Gaussian inputs", "signals": B, "N": N, "precision": "fp32",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "geometry": geometry},
         "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved_gbps / PEAK_HBM_GBPS, "traffic": traffic,
-                     "kernel": "k_lct<float,16,4096,fwd>", "kernel_ms": ms_kernel,
+                     "kernel": "k_lct (FP32, forward)", "kernel_ms": ms_kernel,
                      "algorithmic_bytes_per_launch": algo_bytes},
         "wall_s_timed": wall,
         "fp64_path": fp64,
+        "tuning": tuning,
     }
 
     if not args.no_cpu_baseline:

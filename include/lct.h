@@ -186,6 +186,49 @@ int lct_exec_ragged(lct_ragged_plan p, const lct_desc *d_desc, const void *in, v
 void lct_ragged_plan_destroy(lct_ragged_plan p);
 
 /*
+ * Autotuner.  The launch geometry of a transform (values per thread, signals
+ * per work-group and the radix order of the FFT stages; for two-pass sizes the
+ * split N = N1 N2 and the column and row tile widths) comes from a
+ * process-wide table keyed by (kind, N, precision) when it holds an entry,
+ * otherwise from a built-in heuristic.  It applies to lct_exec,
+ * lct_exec_many, the adjoints and the fractional transform (whose geometry is
+ * that of its length-2N convolution); results do not depend on it beyond
+ * rounding.
+ *
+ * lct_autotune times every candidate geometry on the current device (ten
+ * launches each after two warm-ups, on `batch` signals of scratch device
+ * memory that it allocates and frees; batch 0 means about 2^24 samples),
+ * records the fastest in the table and fills *res (may be NULL).  It
+ * synchronises `stream`.  Entries are single text lines,
+ *   lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16
+ *   lct N=1048576 prec=fp32 N1=1024 E1=16 E2=16 C=16 RR=16 rad1=16.16.4 rad2=16.16.4
+ * ("frft" for the fractional transform); every field is validated against
+ * the kernels' preconditions, and an invalid line gives LCT_ERR_ARG.
+ *   lct_tune_candidates  the candidate lines, '\n'-separated, into buf (host)
+ *   lct_tune_get         the line in use for (kind, N, precision) (host)
+ *   lct_tune_set         records one line (host)
+ *   lct_tune_load/save   reads / writes a file of lines ('#' comments); a file
+ *                        with any invalid line is rejected as a whole
+ *   lct_tune_clear       empties the table
+ */
+enum { LCT_TUNE_LCT = 0, LCT_TUNE_FRFT = 1 };
+typedef struct {
+    int32_t kind;       /* LCT_TUNE_LCT or LCT_TUNE_FRFT */
+    int32_t candidates; /* geometries timed */
+    double best_us;     /* mean time of one execution with the chosen geometry */
+    double default_us;  /* same with the heuristic's geometry */
+    int64_t batch;      /* signals per timed execution */
+    char config[160];   /* the chosen entry line */
+} lct_tune_result;
+int lct_autotune(int64_t N, lct_precision prec, int kind, int64_t batch, hipStream_t stream, lct_tune_result *res);
+int lct_tune_candidates(int64_t N, lct_precision prec, int kind, char *buf, size_t cap, int *count);
+int lct_tune_get(int64_t N, lct_precision prec, int kind, char *buf, size_t cap);
+int lct_tune_set(const char *line);
+int lct_tune_load(const char *path);
+int lct_tune_save(const char *path);
+void lct_tune_clear(void);
+
+/*
  * Host helper: input nodes x (N doubles, eq. asymcer) and output nodes y
  * (N doubles: 4 b x_j / pi, or x_j / d when b == 0).  Either pointer may be NULL.
  * Host memory.  Returns LCT_ERR_ARG for N < 1 or b == d == 0.

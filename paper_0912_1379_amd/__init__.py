@@ -35,13 +35,15 @@ import torch
 from . import _lib
 from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODULAR,  # noqa: F401
                    LCT_ERR_UNSUPPORTED, LCT_ERR_UNSUPPORTED_N, LCT_ERR_WORKSPACE, LCT_FP32, LCT_FP64,
-                   LCT_OK, LctError)
+                   LCT_OK, LCT_TUNE_FRFT, LCT_TUNE_LCT, LctError)
 
 __all__ = [
     "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
     "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
     "frft_workspace_size", "RaggedPlan", "make_descriptors", "lct_ragged_plan_create", "lct_exec_ragged",
     "LCT_KIND_LCT", "LCT_KIND_FRFT",
+    "lct_autotune", "lct_tune_candidates", "lct_tune_get", "lct_tune_set", "lct_tune_load", "lct_tune_save",
+    "lct_tune_clear", "LCT_TUNE_LCT", "LCT_TUNE_FRFT",
     "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
     "LCT_FP32", "LCT_FP64",
 ]
@@ -326,6 +328,61 @@ def lct_exec_ragged(plan: RaggedPlan, x: torch.Tensor, out=None, ws=None, stream
                                      ws.numel() - (aligned - base), _stream_handle(stream))
     _lib.check(rc, "lct_exec_ragged")
     return out
+
+
+def _tune_kind(kind) -> int:
+    if kind in ("lct", LCT_TUNE_LCT):
+        return LCT_TUNE_LCT
+    if kind in ("frft", LCT_TUNE_FRFT):
+        return LCT_TUNE_FRFT
+    raise ValueError(f"unknown transform kind {kind!r}")
+
+
+def lct_autotune(N: int, precision: int = LCT_FP32, kind="lct", batch: int = 0, stream=None) -> dict:
+    """Times every candidate launch geometry for (kind, N, precision) on the
+    current device, records the fastest in the library's table and returns
+    what was measured (synchronises the stream)."""
+    res = _lib.TuneResult()
+    rc = _lib.load().lct_autotune(int(N), int(precision), _tune_kind(kind), int(batch), _stream_handle(stream),
+                                  ctypes.byref(res))
+    _lib.check(rc, "lct_autotune")
+    return {"config": res.config.decode(), "candidates": res.candidates, "best_us": res.best_us,
+            "default_us": res.default_us, "batch": res.batch}
+
+
+def lct_tune_candidates(N: int, precision: int = LCT_FP32, kind="lct") -> list:
+    """The candidate geometries (entry lines) the autotuner would time."""
+    lib = _lib.load()
+    n = ctypes.c_int(0)
+    buf = ctypes.create_string_buffer(1 << 16)
+    _lib.check(lib.lct_tune_candidates(int(N), int(precision), _tune_kind(kind), buf, len(buf), ctypes.byref(n)),
+               "lct_tune_candidates")
+    lines = [ln for ln in buf.value.decode().split("\n") if ln]
+    assert len(lines) == n.value
+    return lines
+
+
+def lct_tune_get(N: int, precision: int = LCT_FP32, kind="lct") -> str:
+    """The geometry line the entry points use for (kind, N, precision)."""
+    buf = ctypes.create_string_buffer(512)
+    _lib.check(_lib.load().lct_tune_get(int(N), int(precision), _tune_kind(kind), buf, len(buf)), "lct_tune_get")
+    return buf.value.decode()
+
+
+def lct_tune_set(line: str) -> None:
+    _lib.check(_lib.load().lct_tune_set(line.encode()), "lct_tune_set")
+
+
+def lct_tune_load(path: str) -> None:
+    _lib.check(_lib.load().lct_tune_load(str(path).encode()), "lct_tune_load")
+
+
+def lct_tune_save(path: str) -> None:
+    _lib.check(_lib.load().lct_tune_save(str(path).encode()), "lct_tune_save")
+
+
+def lct_tune_clear() -> None:
+    _lib.load().lct_tune_clear()
 
 
 def lct_nodes(N: int, b: float, d: float = 1.0):

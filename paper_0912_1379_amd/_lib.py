@@ -25,6 +25,15 @@ LCT_ERR_UNSUPPORTED = -7
 LCT_FP32 = 0
 LCT_FP64 = 1
 
+LCT_TUNE_LCT = 0
+LCT_TUNE_FRFT = 1
+
+
+class TuneResult(ctypes.Structure):
+    """lct_tune_result of include/lct.h."""
+    _fields_ = [("kind", ctypes.c_int32), ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double),
+                ("default_us", ctypes.c_double), ("batch", ctypes.c_int64), ("config", ctypes.c_char * 160)]
+
 _lib = None
 
 _vp = ctypes.c_void_p
@@ -53,6 +62,13 @@ SIGNATURES = {
     "lct_ragged_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_size_t)]),
     "lct_exec_ragged": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lct_ragged_plan_destroy": (None, [_vp]),
+    "lct_autotune": (_int, [_i64, _int, _int, _i64, _vp, _vp]),
+    "lct_tune_candidates": (_int, [_i64, _int, _int, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_int)]),
+    "lct_tune_get": (_int, [_i64, _int, _int, ctypes.c_char_p, ctypes.c_size_t]),
+    "lct_tune_set": (_int, [ctypes.c_char_p]),
+    "lct_tune_load": (_int, [ctypes.c_char_p]),
+    "lct_tune_save": (_int, [ctypes.c_char_p]),
+    "lct_tune_clear": (None, []),
     "lct_nodes": (_int, [_i64, _d, _d, _dp, _dp]),
     "lct_strerror": (ctypes.c_char_p, [_int]),
     "lct_max_single_pass": (_i64, [_int]),

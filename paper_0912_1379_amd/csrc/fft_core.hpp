@@ -86,12 +86,17 @@ template <> struct Buf<double> {
         u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
         return {__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z)};
     }
+    // The offset goes into the VGPR operand with a zero SGPR offset: with a
+    // register soffset the compiler (ROCm 7.2) omits the wait state a
+    // 128-bit store needs before its data VGPRs may be overwritten, and on
+    // gfx950 the low dwords of some lanes were then stored from the next
+    // value written to those registers.
     static __device__ __forceinline__ void store(C<double> a, __amdgpu_buffer_rsrc_t r, int voff, int soff)
     {
         unsigned long long x = (unsigned long long)__double_as_longlong(a.x);
         unsigned long long y = (unsigned long long)__double_as_longlong(a.y);
         u32x4 v = {(unsigned)x, (unsigned)(x >> 32), (unsigned)y, (unsigned)(y >> 32)};
-        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff + soff, 0, 0);
     }
 };
 

@@ -7,7 +7,9 @@ namespace lctk {
 hipError_t dispatch_lct_f32(int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,
                             hipStream_t s)
 {
-    if (a.N == 4096 && E == 16)
+    // compile-time schedule for the geometry E=16 S=1 rad=16.16.16 of N = 4096
+    // (that kernel assumes one signal per work-group)
+    if (a.N == 4096 && E == 16 && a.S == 1 && a.sc.nst == 3 && a.sc.rad[0] == 16 && a.sc.rad[1] == 16 && a.sc.rad[2] == 16)
         return launch_lct_t<float, 16, 4096>(in, out, a, nb, bs, lds, s);
     switch (E) {
 #define X(e)                                                                                                         \

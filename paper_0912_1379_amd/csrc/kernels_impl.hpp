@@ -103,9 +103,9 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
     const int N = NFIX > 0 ? NFIX : args.N;
     const int T = NFIX > 0 ? NFIX / E : args.T;
 
-    // With T >= 256 threads per signal the host launches one signal per
-    // work-group; saying so at compile time keeps the signal index uniform
-    // (scalar loads of its parameters).
+    // The fixed-size instantiation is launched with one signal per
+    // work-group (T = NFIX / E >= 256 threads); saying so at compile time
+    // keeps the signal index uniform (scalar loads of its parameters).
     constexpr bool ONE = NFIX > 0 && NFIX / E >= 256;
     const int sl = ONE ? 0 : (int)threadIdx.x / T; // signal slot within the work-group
     const int t = (int)threadIdx.x - sl * T;
@@ -424,6 +424,5 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
     return hipGetLastError();
 }
 
-#define LCT_E_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30)
 
 } // namespace lctk

@@ -7,7 +7,7 @@
 #include <new>
 
 #include "../../include/lct.h"
-#include "lct_kernels.hpp"
+#include "plan.hpp"
 
 using namespace lctk;
 
@@ -20,196 +20,122 @@ struct lct_plan_s {
 
 namespace {
 
-constexpr int64_t MAX_N = int64_t(1) << 24;
-constexpr size_t LDS_BYTES = 160 * 1024;
-
-bool smooth235(int64_t N)
-{
-    if (N < 1 || N > MAX_N)
-        return false;
-    for (int p : {2, 3, 5})
-        while (N % p == 0)
-            N /= p;
-    return N == 1;
-}
-
-// Elements per thread: the first E of the list for the size's prime set that
-// divides N and keeps the thread count per signal within a work-group.
-int choose_E(int64_t N, bool fp64, bool frft)
-{
-    int64_t m = N;
-    bool p2 = false, p3 = false, p5 = false;
-    while (m % 2 == 0) { m /= 2; p2 = true; }
-    while (m % 3 == 0) { m /= 3; p3 = true; }
-    while (m % 5 == 0) { m /= 5; p5 = true; }
-    static const int l2[] = {16, 8, 4, 2, 0};
-    static const int l3[] = {27, 9, 3, 0};
-    static const int l5[] = {25, 5, 0};
-    static const int l23[] = {24, 12, 6, 18, 0};
-    static const int l25[] = {20, 10, 0};
-    static const int l35[] = {15, 0};
-    static const int l235[] = {30, 0};
-    static const int l1[] = {1, 0};
-    static const int l2_64[] = {16, 8, 4, 2, 0};
-    static const int l23_64[] = {12, 6, 24, 18, 0};
-    static const int l25_64[] = {10, 20, 0};
-    static const int l2_fr[] = {16, 8, 4, 2, 0};
-    static const int l2_fr64[] = {8, 16, 4, 2, 0};
-    const int *lst;
-    if (p2 && p3 && p5) lst = l235;
-    else if (p2 && p3) lst = fp64 ? l23_64 : l23;
-    else if (p2 && p5) lst = fp64 ? l25_64 : l25;
-    else if (p3 && p5) lst = l35;
-    else if (p2) lst = frft ? (fp64 ? l2_fr64 : l2_fr) : (fp64 ? l2_64 : l2);
-    else if (p3) lst = l3;
-    else if (p5) lst = l5;
-    else lst = l1;
-    for (int i = 0; lst[i]; ++i) {
-        int E = lst[i];
-        if (N % E == 0 && N / E <= max_block(fp64, E))
-            return E;
-    }
-    return 0;
-}
-
-Sched make_sched(int64_t N, int E)
-{
-    Sched s{};
-    s.nst = 0;
-    int64_t rem = N;
-    const int cand[6] = {16, 8, 5, 4, 3, 2};
-    while (rem > 1 && s.nst < 24) {
-        bool ok = false;
-        for (int c : cand) {
-            if (E % c == 0 && rem % c == 0) {
-                s.rad[s.nst++] = c;
-                rem /= c;
-                ok = true;
-                break;
-            }
-        }
-        if (!ok)
-            break;
-    }
-    if (rem != 1)
-        s.nst = -1;
-    return s;
-}
-
-struct Tiling {
-    int E = 0, T = 0, S = 0, block = 0;
-    size_t lds = 0;
-    Sched sc{};
-    bool ok = false;
-};
-
-// Length Nfft DFT held in LDS; `extra` bytes per signal slot after the FFT area.
-Tiling make_tiling(int64_t Nfft, bool fp64, bool frft, size_t extra)
-{
-    Tiling t;
-    t.E = choose_E(Nfft, fp64, frft);
-    if (t.E == 0)
-        return t;
-    t.T = (int)(Nfft / t.E);
-    t.sc = make_sched(Nfft, t.E);
-    if (t.sc.nst < 0)
-        return t;
-    const size_t elem = fp64 ? 16 : 8;
-    const size_t per = (size_t)lds_elems((int)Nfft) * elem;
-    int S = t.T >= 256 ? 1 : 256 / t.T;
-    if (S < 1)
-        S = 1;
-    while (S > 1 && S * (per + extra) > LDS_BYTES)
-        --S;
-    if (per + extra > LDS_BYTES)
-        return t;
-    t.S = S;
-    t.block = S * t.T;
-    t.lds = S * per + S * extra;
-    t.ok = t.block <= max_block(fp64, t.E);
-    return t;
-}
-
-int hip_status(hipError_t e);
-
-// Two-pass (four-step) plan for N beyond one work-group: N = N1 N2 with N1 the
-// largest divisor <= sqrt(N) whose tiles fit; C columns per pass-1 group and
-// RR rows per pass-2 group, as many as keep >= 128-byte row segments and fit
-// LDS and the launch bound.
-struct FsTiling {
-    int N1 = 0, N2 = 0, E1 = 0, E2 = 0, T1 = 0, T2 = 0, C = 0, RR = 0, bs1 = 0, bs2 = 0;
-    size_t lds1 = 0, lds2 = 0;
-    Sched sc1{}, sc2{};
-    bool ok = false;
-};
-
-int pick_group(int Nsub, int T, int E, int other, bool fp64)
-{
-    const size_t elem = fp64 ? 16 : 8;
-    const size_t per = (size_t)lds_elems(Nsub) * elem;
-    const int want = fp64 ? 8 : 16;          // >= 128 B per row segment
-    int cap = 256 / T > want ? 256 / T : want; // ~256 threads when T is small
-    if (cap > 64)
-        cap = 64;
-    for (int c = cap; c >= 1; --c) {
-        if (other % c)
-            continue;
-        if (c * T > max_block(fp64, E) || c * per > LDS_BYTES)
-            continue;
-        return c;
-    }
-    return 0;
-}
-
-FsTiling make_fs(int64_t N, bool fp64)
-{
-    FsTiling f;
-    int64_t best = 0;
-    for (int64_t d = 1; d * d <= N; ++d)
-        if (N % d == 0)
-            best = d;
-    for (int64_t N1 = best; N1 >= 2; --N1) {
-        if (N % N1)
-            continue;
-        const int64_t N2 = N / N1;
-        if (N1 > 16384 || N2 > 16384)
-            break;
-        f.N1 = (int)N1;
-        f.N2 = (int)N2;
-        f.E1 = choose_E(N1, fp64, false);
-        f.E2 = choose_E(N2, fp64, false);
-        if (!f.E1 || !f.E2)
-            continue;
-        f.T1 = (int)(N1 / f.E1);
-        f.T2 = (int)(N2 / f.E2);
-        f.sc1 = make_sched(N1, f.E1);
-        f.sc2 = make_sched(N2, f.E2);
-        if (f.sc1.nst < 0 || f.sc2.nst < 0)
-            continue;
-        f.C = pick_group((int)N1, f.T1, f.E1, (int)N2, fp64);
-        f.RR = pick_group((int)N2, f.T2, f.E2, (int)N1, fp64);
-        if (!f.C || !f.RR)
-            continue;
-        const size_t elem = fp64 ? 16 : 8;
-        f.bs1 = f.C * f.T1;
-        f.bs2 = f.RR * f.T2;
-        f.lds1 = (size_t)f.C * lds_elems((int)N1) * elem;
-        f.lds2 = (size_t)f.RR * lds_elems((int)N2) * elem;
-        f.ok = true;
-        return f;
-    }
-    f.ok = false;
-    return f;
-}
-
 int fs_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
            int64_t batch, hipStream_t s)
 {
     if (in == out)
         return LCT_ERR_ARG; // pass 1 reads columns of `in` while writing rows of `out`
-    FsTiling f = make_fs(N, fp64);
+    const FsTiling f = select_fs(LCT_TUNE_LCT, N, N, fp64);
     if (!f.ok)
         return LCT_ERR_UNSUPPORTED;
+    return fs_launch(f, N, fp64, M4, k, mode, in, out, batch, s);
+}
+
+int check_ptr(const void *p, bool fp64)
+{
+    if (p == nullptr)
+        return LCT_ERR_ARG;
+    if (((uintptr_t)p) % (fp64 ? 16 : 8) != 0)
+        return LCT_ERR_ARG;
+    return LCT_OK;
+}
+
+int validate_M(double a, double b, double c, double d)
+{
+    if (!isfinite(a) || !isfinite(b) || !isfinite(c) || !isfinite(d))
+        return LCT_ERR_ARG;
+    double ad = a * d, bc = b * c;
+    double tol = 1e-10 * fmax(1.0, fmax(fabs(ad), fabs(bc)));
+    if (fabs(ad - bc - 1.0) > tol)
+        return LCT_ERR_NOT_UNIMODULAR;
+    return LCT_OK;
+}
+
+int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
+            int64_t batch, hipStream_t s)
+{
+    if (batch < 0)
+        return LCT_ERR_ARG;
+    if (!smooth235(N))
+        return LCT_ERR_UNSUPPORTED_N;
+    if (batch == 0)
+        return LCT_OK;
+    int rc;
+    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
+        return rc;
+    if (N > single_pass_limit(fp64))
+        return fs_run(N, fp64, M4, k, mode, in, out, batch, s);
+    const Tiling tl = select_tiling(LCT_TUNE_LCT, N, N, fp64, 0);
+    if (!tl.ok)
+        return LCT_ERR_UNSUPPORTED;
+    return lct_launch(tl, N, fp64, M4, k, mode, in, out, batch, s);
+}
+
+size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
+{
+    if (2 * N <= single_pass_limit(fp64))
+        return 0;
+    return (size_t)batch * 2 * (size_t)(2 * N) * (fp64 ? 16 : 8);
+}
+
+int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
+             void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (batch < 0)
+        return LCT_ERR_ARG;
+    if (!smooth235(N))
+        return LCT_ERR_UNSUPPORTED_N;
+    if (batch == 0)
+        return LCT_OK;
+    int rc;
+    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
+        return rc;
+    if (in == out)
+        return LCT_ERR_ARG; // the Hankel form reads the input reversed
+    if (2 * N > single_pass_limit(fp64)) {
+        const size_t need = frft_ws_bytes(N, fp64, batch);
+        if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws) % 16)
+            return LCT_ERR_WORKSPACE;
+        const FsTiling f = select_fs(LCT_TUNE_FRFT, N, 2 * N, fp64);
+        if (!f.ok)
+            return LCT_ERR_UNSUPPORTED;
+        return frft_large_launch(f, N, fp64, Z2, k, in, out, batch, ws, s);
+    }
+    const Tiling tl = select_tiling(LCT_TUNE_FRFT, N, 2 * N, fp64, 0);
+    if (!tl.ok)
+        return LCT_ERR_UNSUPPORTED;
+    return frft_sp_launch(tl, N, fp64, Z2, k, in, out, batch, s);
+}
+
+} // namespace
+
+namespace lctk {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? LCT_OK : LCT_ERR_HIP; }
+
+int lct_launch(const Tiling &tl, int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in,
+               void *out, int64_t batch, hipStream_t s)
+{
+    LctArgs a{};
+    a.N = (int)N;
+    a.T = tl.T;
+    a.S = tl.S;
+    a.mode = mode;
+    a.batch = batch;
+    a.M4 = M4;
+    if (k)
+        a.k = *k;
+    a.nc = n_const_host(N);
+    a.sc = tl.sc;
+    const int64_t nb = (batch + tl.S - 1) / tl.S;
+    if (nb > INT32_MAX)
+        return LCT_ERR_ARG;
+    return hip_status(launch_lct(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
+}
+
+int fs_launch(const FsTiling &f, int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in,
+              void *out, int64_t batch, hipStream_t s)
+{
     FsArgs a{};
     a.N = (int)N;
     a.N1 = f.N1;
@@ -235,75 +161,27 @@ int fs_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, 
     return hip_status(launch_fs2(fp64, f.E2, out, a, (int)nb2, f.bs2, f.lds2, s));
 }
 
-int check_ptr(const void *p, bool fp64)
+int frft_sp_launch(const Tiling &tl, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
+                   void *out, int64_t batch, hipStream_t s)
 {
-    if (p == nullptr)
-        return LCT_ERR_ARG;
-    if (((uintptr_t)p) % (fp64 ? 16 : 8) != 0)
-        return LCT_ERR_ARG;
-    return LCT_OK;
-}
-
-int hip_status(hipError_t e) { return e == hipSuccess ? LCT_OK : LCT_ERR_HIP; }
-
-int validate_M(double a, double b, double c, double d)
-{
-    if (!isfinite(a) || !isfinite(b) || !isfinite(c) || !isfinite(d))
-        return LCT_ERR_ARG;
-    double ad = a * d, bc = b * c;
-    double tol = 1e-10 * fmax(1.0, fmax(fabs(ad), fabs(bc)));
-    if (fabs(ad - bc - 1.0) > tol)
-        return LCT_ERR_NOT_UNIMODULAR;
-    return LCT_OK;
-}
-
-int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
-            int64_t batch, hipStream_t s)
-{
-    if (batch < 0)
-        return LCT_ERR_ARG;
-    if (!smooth235(N))
-        return LCT_ERR_UNSUPPORTED_N;
-    if (batch == 0)
-        return LCT_OK;
-    int rc;
-    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
-        return rc;
-    if (N > lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
-        return fs_run(N, fp64, M4, k, mode, in, out, batch, s);
-    Tiling tl = make_tiling(N, fp64, false, 0);
-    if (!tl.ok)
-        return LCT_ERR_UNSUPPORTED;
-    LctArgs a{};
+    FrArgs a{};
     a.N = (int)N;
     a.T = tl.T;
     a.S = tl.S;
-    a.mode = mode;
     a.batch = batch;
-    a.M4 = M4;
+    a.Z2 = Z2;
     if (k)
         a.k = *k;
-    a.nc = n_const_host(N);
     a.sc = tl.sc;
-    int64_t nb = (batch + tl.S - 1) / tl.S;
+    const int64_t nb = (batch + tl.S - 1) / tl.S;
     if (nb > INT32_MAX)
         return LCT_ERR_ARG;
-    return hip_status(launch_lct(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
+    return hip_status(launch_frft(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
 }
 
-size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
+int frft_large_launch(const FsTiling &f, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
+                      void *out, int64_t batch, void *ws, hipStream_t s)
 {
-    if (2 * N <= lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32))
-        return 0;
-    return (size_t)batch * 2 * (size_t)(2 * N) * (fp64 ? 16 : 8);
-}
-
-int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
-               void *ws, hipStream_t s)
-{
-    FsTiling f = make_fs(2 * N, fp64);
-    if (!f.ok)
-        return LCT_ERR_UNSUPPORTED;
     FrLArgs a{};
     a.N = (int)N;
     a.L = (int)(2 * N);
@@ -320,7 +198,7 @@ int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const v
     a.sc1 = f.sc1;
     a.sc2 = f.sc2;
     const int64_t nb1 = batch * (f.N2 / f.C), nb2 = batch * (f.N1 / f.RR);
-    if (2 * nb1 > INT32_MAX || 2 * nb2 > INT32_MAX || batch > INT32_MAX)
+    if (2 * nb1 > INT32_MAX || nb2 > INT32_MAX || batch > INT32_MAX)
         return LCT_ERR_ARG;
     hipError_t e;
     if ((e = launch_frl1(fp64, f.E1, in, ws, a, (int)(2 * nb1), f.bs1, f.lds1, s)) != hipSuccess ||
@@ -332,53 +210,11 @@ int frft_large(int64_t N, bool fp64, const double *Z2, const FrConst *k, const v
     return LCT_OK;
 }
 
-int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
-             void *ws, size_t ws_bytes, hipStream_t s)
-{
-    if (batch < 0)
-        return LCT_ERR_ARG;
-    if (!smooth235(N))
-        return LCT_ERR_UNSUPPORTED_N;
-    if (batch == 0)
-        return LCT_OK;
-    int rc;
-    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
-        return rc;
-    if (in == out)
-        return LCT_ERR_ARG; // the Hankel form reads the input reversed
-    if (2 * N > lct_max_single_pass(fp64 ? LCT_FP64 : LCT_FP32)) {
-        const size_t need = frft_ws_bytes(N, fp64, batch);
-        if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws) % 16)
-            return LCT_ERR_WORKSPACE;
-        return frft_large(N, fp64, Z2, k, in, out, batch, ws, s);
-    }
-    Tiling tl = make_tiling(2 * N, fp64, true, 0);
-    if (!tl.ok)
-        return LCT_ERR_UNSUPPORTED;
-    FrArgs a{};
-    a.N = (int)N;
-    a.T = tl.T;
-    a.S = tl.S;
-    a.batch = batch;
-    a.Z2 = Z2;
-    if (k)
-        a.k = *k;
-    a.sc = tl.sc;
-    int64_t nb = (batch + tl.S - 1) / tl.S;
-    if (nb > INT32_MAX)
-        return LCT_ERR_ARG;
-    return hip_status(launch_frft(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
-}
-
-} // namespace
+} // namespace lctk
 
 extern "C" {
 
-int64_t lct_max_single_pass(lct_precision prec)
-{
-    // largest 2^p 3^q 5^r whose padded LDS image fits 160 KiB with <= 1024 threads
-    return prec == LCT_FP64 ? 8192 : 16384;
-}
+int64_t lct_max_single_pass(lct_precision prec) { return single_pass_limit(prec == LCT_FP64); }
 
 int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, double d, lct_precision prec)
 {
@@ -470,7 +306,7 @@ int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const v
         return LCT_ERR_ARG;
     if (N > lct_max_single_pass(prec))
         return LCT_ERR_UNSUPPORTED;
-    Tiling tl = make_tiling(N, fp64, false, 3 * sizeof(double));
+    const Tiling tl = default_tiling(N, fp64, false, 3 * sizeof(double));
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;
     LctArgs a{};

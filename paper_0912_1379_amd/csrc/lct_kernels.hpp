@@ -46,6 +46,9 @@ struct FsArgs {
     Sched sc1, sc2;
 };
 
+// Values per thread (E) with instantiated kernels.
+#define LCT_E_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30)
+
 // Largest work-group a kernel instantiation accepts (its launch bound): the
 // register budget per thread is 512 / (waves per SIMD) VGPRs, so larger E
 // (more values per thread) gets a smaller bound.

@@ -92,3 +92,128 @@ def test_nodes_helper_matches_oracle(lib, N, b, d):
     assert np.allclose(x, oracle.nodes(N), rtol=0, atol=1e-13)
     assert np.allclose(y, oracle.output_nodes(N, b, d), rtol=1e-15, atol=1e-13)
     assert lib.lct_nodes(0, 1.0, 1.0, None, None) == _lib.LCT_ERR_ARG
+
+
+# --- autotuner table (host functions only) ------------------------------------
+def _cands(lib, N, prec, kind):
+    n = ctypes.c_int(0)
+    buf = ctypes.create_string_buffer(1 << 16)
+    assert lib.lct_tune_candidates(N, prec, kind, buf, len(buf), ctypes.byref(n)) == _lib.LCT_OK
+    lines = [ln for ln in buf.value.decode().split("\n") if ln]
+    assert len(lines) == n.value
+    return lines
+
+
+def _get(lib, N, prec, kind):
+    buf = ctypes.create_string_buffer(512)
+    assert lib.lct_tune_get(N, prec, kind, buf, len(buf)) == _lib.LCT_OK
+    return buf.value.decode()
+
+
+TUNE_SIZES = [(1, 0, 0), (64, 0, 0), (1000, 0, 0), (4096, 0, 0), (4096, 1, 0), (6000, 1, 0), (16384, 0, 0),
+              (32768, 0, 0), (1 << 20, 0, 0), (1 << 20, 1, 0), (3 * 5 * 2 ** 12, 0, 0), (2048, 0, 1),
+              (8192, 0, 1), (12288, 0, 1), (40960, 1, 1)]
+
+
+@pytest.mark.parametrize("N,prec,kind", TUNE_SIZES)
+def test_tune_candidates_are_valid_entries(lib, N, prec, kind):
+    lib.lct_tune_clear()
+    lines = _cands(lib, N, prec, kind)
+    assert lines, N
+    assert len(set(lines)) == len(lines)
+    # the first candidate is the heuristic's own choice
+    assert lines[0] == _get(lib, N, prec, kind)
+    for ln in lines:
+        assert lib.lct_tune_set(ln.encode()) == _lib.LCT_OK, ln
+        assert _get(lib, N, prec, kind) == ln
+    lib.lct_tune_clear()
+    assert _get(lib, N, prec, kind) == lines[0]
+
+
+def _two_pass_fields(line):
+    kv = dict(tok.split("=") for tok in line.split()[1:])
+    return kv
+
+
+def test_tune_candidate_geometry_invariants(lib):
+    """Two-pass candidates split N exactly and tile whole columns / rows;
+    one-pass candidates have radices that divide E and multiply to N."""
+    for N, prec, kind in TUNE_SIZES:
+        Nfft = 2 * N if kind == 1 else N
+        for ln in _cands(lib, N, prec, kind):
+            kv = _two_pass_fields(ln)
+            if "N1" in kv:
+                N1, C, RR = int(kv["N1"]), int(kv["C"]), int(kv["RR"])
+                N2 = Nfft // N1
+                assert N1 * N2 == Nfft and N2 % C == 0 and N1 % RR == 0, ln
+                for key, n, E in (("rad1", N1, int(kv["E1"])), ("rad2", N2, int(kv["E2"]))):
+                    r = [int(v) for v in kv[key].split(".")]
+                    assert int(np.prod(r)) == n and all(E % x == 0 for x in r), ln
+            else:
+                E = int(kv["E"])
+                r = [int(v) for v in kv["rad"].split(".")] if kv["rad"] else []
+                assert int(np.prod(r)) == Nfft and all(E % x == 0 for x in r), ln
+
+
+BAD_LINES = [
+    "lct N=4096 prec=fp32 E=7 S=1 rad=16.16.16",          # E not instantiated
+    "lct N=4096 prec=fp32 E=16 S=8 rad=16.16.16",         # 8 x 256 threads > launch bound
+    "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.8",          # radices multiply to 2048
+    "lct N=4096 prec=fp32 E=8 S=1 rad=16.16.16",          # radix 16 does not divide E = 8
+    "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16 X=1",     # unknown field
+    "lct N=4096 prec=fp32 E=16 S=1",                      # no schedule
+    "frft N=4096 prec=fp32 E=16 S=1 rad=16.16.16",        # frft geometry is for length 2N
+    "lct N=4097 prec=fp32 E=1 S=1 rad=",                  # N not 2^p 3^q 5^r
+    "lct N=4096 prec=fp16 E=16 S=1 rad=16.16.16",         # unknown precision
+    "fft N=4096 prec=fp32 E=16 S=1 rad=16.16.16",         # unknown kind
+    "lct N=4096 prec=fp32 E=16 S=0 rad=16.16.16",         # no slot
+    "lct N=1048576 prec=fp32 E=16 S=1 rad=16.16.16.16.16",  # two-pass size needs a split
+    "lct N=1048576 prec=fp32 N1=1000 E1=8 E2=16 C=8 RR=8 rad1=8.8.8.2 rad2=16.16.4",  # N1 does not divide N
+    "lct N=1048576 prec=fp32 N1=1024 E1=16 E2=16 C=24 RR=16 rad1=16.16.4 rad2=16.16.4",  # C does not divide N2
+    "lct N=1048576 prec=fp32 N1=1024 E1=16 E2=16 C=16 RR=16 rad1=16.16.4 rad2=16.16.2",  # rad2 product
+    "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16.1",       # radix 1 not implemented
+    "lct N=4096 prec=fp32 E=-16 S=1 rad=16.16.16",        # negative
+]
+
+
+@pytest.mark.parametrize("line", BAD_LINES)
+def test_tune_rejects_invalid_entries(lib, line):
+    lib.lct_tune_clear()
+    assert lib.lct_tune_set(line.encode()) == _lib.LCT_ERR_ARG
+    assert _get(lib, 4096, 0, 0) == "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16"
+
+
+def test_tune_save_load_round_trip(lib, tmp_path):
+    lib.lct_tune_clear()
+    picks = [_cands(lib, 4096, 0, 0)[3], _cands(lib, 1 << 20, 0, 0)[2], _cands(lib, 2048, 0, 1)[1]]
+    for ln in picks:
+        assert lib.lct_tune_set(ln.encode()) == 0
+    path = tmp_path / "tune.txt"
+    assert lib.lct_tune_save(str(path).encode()) == 0
+    text = path.read_text()
+    assert all(ln in text for ln in picks)
+    lib.lct_tune_clear()
+    assert _get(lib, 4096, 0, 0) != picks[0]
+    assert lib.lct_tune_load(str(path).encode()) == 0
+    assert [_get(lib, 4096, 0, 0), _get(lib, 1 << 20, 0, 0), _get(lib, 2048, 0, 1)] == picks
+    # a file with one invalid line is rejected as a whole
+    lib.lct_tune_clear()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# comment\n" + picks[0] + "\n" + BAD_LINES[0] + "\n")
+    assert lib.lct_tune_load(str(bad).encode()) == _lib.LCT_ERR_ARG
+    assert _get(lib, 4096, 0, 0) == _cands(lib, 4096, 0, 0)[0]
+    assert lib.lct_tune_load(str(tmp_path / "missing.txt").encode()) == _lib.LCT_ERR_ARG
+    lib.lct_tune_clear()
+
+
+def test_tune_argument_errors(lib):
+    buf = ctypes.create_string_buffer(8)
+    n = ctypes.c_int(0)
+    assert lib.lct_tune_candidates(4096, 0, 0, buf, len(buf), ctypes.byref(n)) == _lib.LCT_ERR_ARG  # too small
+    assert lib.lct_tune_candidates(4097, 0, 0, None, 0, ctypes.byref(n)) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert lib.lct_tune_candidates(4096, 3, 0, None, 0, ctypes.byref(n)) == _lib.LCT_ERR_ARG
+    assert lib.lct_tune_candidates(4096, 0, 5, None, 0, ctypes.byref(n)) == _lib.LCT_ERR_ARG
+    assert lib.lct_tune_get(4096, 0, 0, buf, len(buf)) == _lib.LCT_ERR_ARG
+    assert lib.lct_tune_set(None) == _lib.LCT_ERR_ARG
+    assert lib.lct_autotune(4096, 0, 7, 0, None, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_autotune(4097, 0, 0, 0, None, None) == _lib.LCT_ERR_UNSUPPORTED_N
