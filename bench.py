@@ -41,6 +41,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def mfma_flops(B: int, N: int) -> float:
+    """Matrix-core flops of one split-BF16 launch: every radix-16 stage runs
+    N / 256 groups of 16 butterflies per signal, six 16x16x32 MFMAs (2 x 16 x
+    16 x 32 flops each) per group."""
+    stages16 = 0
+    n = N
+    while n % 16 == 0 and n > 1:
+        stages16 += 1
+        n //= 16
+    return float(B) * stages16 * (N // 256) * 6 * 2 * 16 * 16 * 32
+
+
 def make_inputs(B: int, N: int, seed_index: int = 1):
     import workloads
     import paper_0912_1379_amd as lct
@@ -78,18 +90,21 @@ def time_launches(fn, steps: int, warmup: int):
     return start.elapsed_time(stop) / steps, per_launch, wall
 
 
-def cpu_baseline(xh: np.ndarray, M: np.ndarray, yh: np.ndarray, budget_s: float):
+def cpu_baseline(xh: np.ndarray, M: np.ndarray, outs: dict, budget_s: float):
     """Oracle on a bounded sample of the same workload: whole signals (dense
-    O(N^2) Riemann sums), as many as fit the time budget (at least 2)."""
+    O(N^2) Riemann sums), as many as fit the time budget (at least 2).  Also
+    returns, per signal of the sample, the relative L2 error of every GPU
+    result in `outs` (name -> complex128 array of the batch's outputs)."""
     import oracle
 
     N = xh.shape[1]
     done = 0
-    errs = []
+    errs = {k: [] for k in outs}
     t0 = time.perf_counter()
     while done < xh.shape[0] and (done < 2 or time.perf_counter() - t0 < budget_s):
         ref = oracle.lct(xh[done].astype(np.complex128), *M[done])
-        errs.append(float(np.linalg.norm(yh[done] - ref) / np.linalg.norm(ref)))
+        for k, y in outs.items():
+            errs[k].append(float(np.linalg.norm(y[done] - ref) / np.linalg.norm(ref)))
         done += 1
     el = time.perf_counter() - t0
     return {
@@ -162,6 +177,9 @@ def bench_large(args):
     y32, y64 = torch.empty_like(x32), torch.empty_like(x64)
     ms, ms_kernel, wall = time_launches(lambda: lct.lct_exec_many(x32, M4, out=y32), args.steps, args.warmup)
     ms64, ms64_kernel, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64), max(5, args.steps // 2), 2)
+    ysp = torch.empty_like(x32)
+    mss, mss_kernel, _ = time_launches(lambda: lct.lct_exec_many(x32, M4, out=ysp, precision=lct.LCT_FP32_SPLITBF16),
+                                       max(5, args.steps // 2), 2)
     samples = B * N
     gbps = 16.0 * samples / (ms_kernel * 1e-3) / 1e9
     out = {
@@ -177,21 +195,37 @@ def bench_large(args):
                      "actual_bytes_per_launch_two_pass": 32.0 * samples},
         "wall_s_timed": wall,
         "fp64_path": {"ms_per_step": ms64, "kernel_ms": ms64_kernel, "fp32_speedup": ms64 / ms},
+        "splitbf16_path": {"ms_per_step": mss, "kernel_ms": mss_kernel},
     }
     if not args.no_cpu_baseline:
         import oracle
 
-        rows = np.sort(np.random.default_rng(4).choice(N, 64, replace=False))
-        errs32, errs64 = [], []
+        # rows where the chirped Gaussian's transform has its energy (from the
+        # Gaussian integral's modulus; it only picks rows) plus random rows
+        def energy_rows(s, nrow=64):
+            a, b, c, d = M[s]
+            mu, sigma, kappa = gp[s]
+            al = 1 / (2 * sigma ** 2) - 1j * kappa
+            be = -mu / (2 * sigma ** 2)
+            _, yn = lct.lct_nodes(N, b, d)
+            logmag = np.real((be + 1j * yn / (2 * b)) ** 2 / (al - 1j * a / (2 * b)))
+            top = np.argsort(-logmag)[: nrow // 2]
+            rnd = np.random.default_rng(4 + s).choice(N, nrow - nrow // 2, replace=False)
+            return np.unique(np.concatenate([top, rnd]))
+        errs32, errs64, errsp = [], [], []
         t0 = time.perf_counter()
         for s in range(2):
+            rows = energy_rows(s)
             fin = x32[s].cpu().numpy().astype(np.complex128)
             ref = oracle.lct(fin, *M[s], rows=rows)
             errs32.append(float(np.linalg.norm(y32[s].cpu().numpy()[rows] - ref) / np.linalg.norm(ref)))
+            errsp.append(float(np.linalg.norm(ysp[s].cpu().numpy()[rows] - ref) / np.linalg.norm(ref)))
             ref64 = oracle.lct(x64[s].cpu().numpy(), *M[s], rows=rows)
             errs64.append(float(np.linalg.norm(y64[s].cpu().numpy()[rows] - ref64) / np.linalg.norm(ref64)))
         el = time.perf_counter() - t0
-        out["rel_l2_sampled"] = {"fp32_max": max(errs32), "fp64_max": max(errs64), "rows": 64, "signals": 2}
+        out["rel_l2_sampled"] = {"fp32_max": max(errs32), "fp64_max": max(errs64), "splitbf16_max": max(errsp),
+                                 "rows": "64 per signal (32 where the output has its energy, 32 random)",
+                                 "signals": 2}
         out["cpu_baseline"] = {"value": 2 * 2 * 64 / el, "unit": "output samples/s (dense rows of 2^20 terms)",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": f"2 signals x 64 rows, FP32 and FP64 inputs, {el:.1f} s"}
@@ -246,6 +280,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 matrix-core variant")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
     ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit"], default="batched",
@@ -307,6 +342,19 @@ def main():
         print(f"[bench] fp64: {ms64 * 1e3:.1f} us/step", file=sys.stderr, flush=True)
         del x64, y64
 
+    split = None
+    ysp = None
+    if not args.no_split:
+        ysp = torch.empty_like(x32)
+        mss, mss_kernel, _ = time_launches(
+            lambda: lct.lct_exec_many(x32, M4, out=ysp, precision=lct.LCT_FP32_SPLITBF16), max(5, args.steps // 2), 3)
+        split = {"ms_per_step": mss, "value": samples / (mss * 1e-3), "kernel_ms": mss_kernel,
+                 "achieved_GBps": 16.0 * samples / (mss_kernel * 1e-3) / 1e9,
+                 "mfma_flops_per_launch": mfma_flops(B, N),
+                 "mfma_TFLOPs": mfma_flops(B, N) / (mss_kernel * 1e-3) / 1e12,
+                 "kernel": "k_lct (FP32 data, radix-16 stages as split-BF16 MFMA)"}
+        print(f"[bench] split-bf16: {mss * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
@@ -336,16 +384,23 @@ def main():
                      "algorithmic_bytes_per_launch": algo_bytes},
         "wall_s_timed": wall,
         "fp64_path": fp64,
+        "splitbf16_path": split,
         "tuning": tuning,
     }
 
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         xh = x32.cpu().numpy()
-        yh = y32.cpu().numpy().astype(np.complex128)
-        cb, errs = cpu_baseline(xh, M, yh, args.cpu_budget)
+        outs = {"fp32": y32.cpu().numpy().astype(np.complex128)}
+        if ysp is not None:
+            outs["splitbf16"] = ysp.cpu().numpy().astype(np.complex128)
+        cb, errs = cpu_baseline(xh, M, outs, args.cpu_budget)
         out["cpu_baseline"] = cb
-        out["rel_l2"] = {"max": max(errs), "median": float(np.median(errs)), "signals": len(errs)}
+        e32 = errs["fp32"]
+        out["rel_l2"] = {"max": max(e32), "median": float(np.median(e32)), "signals": len(e32)}
+        if split is not None:
+            es = errs["splitbf16"]
+            split["rel_l2"] = {"max": max(es), "median": float(np.median(es)), "signals": len(es)}
     print(json.dumps(out), flush=True)
 
 

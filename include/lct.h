@@ -54,8 +54,17 @@ enum {
 };
 
 typedef enum {
-    LCT_FP32 = 0, /* complex64 data, FP32 FFT, FP64 phase reduction */
-    LCT_FP64 = 1  /* complex128 data, FP64 throughout */
+    LCT_FP32 = 0,          /* complex64 data, FP32 FFT, FP64 phase reduction */
+    LCT_FP64 = 1,          /* complex128 data, FP64 throughout */
+    LCT_FP32_SPLITBF16 = 2 /* complex64 data; the FFT's radix-16 stages run on the
+                              matrix cores as complex 16 x 16 DFT products with
+                              operands split into two BF16 parts (x = hi + lo,
+                              W x ~ W_hi x_hi + W_hi x_lo + W_lo x_hi) and FP32
+                              accumulation, about 16 significant bits per
+                              product; other stages, twiddles and chirps as
+                              LCT_FP32.  LCT only (forward and adjoint), N a
+                              power of two from 256 to 2^24; other requests
+                              return LCT_ERR_UNSUPPORTED. */
 } lct_precision;
 
 typedef struct lct_plan_s *lct_plan;

@@ -35,7 +35,7 @@ import torch
 from . import _lib
 from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODULAR,  # noqa: F401
                    LCT_ERR_UNSUPPORTED, LCT_ERR_UNSUPPORTED_N, LCT_ERR_WORKSPACE, LCT_FP32, LCT_FP64,
-                   LCT_OK, LCT_TUNE_FRFT, LCT_TUNE_LCT, LctError)
+                   LCT_FP32_SPLITBF16, LCT_OK, LCT_TUNE_FRFT, LCT_TUNE_LCT, LctError)
 
 __all__ = [
     "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
@@ -45,7 +45,7 @@ __all__ = [
     "lct_autotune", "lct_tune_candidates", "lct_tune_get", "lct_tune_set", "lct_tune_load", "lct_tune_save",
     "lct_tune_clear", "LCT_TUNE_LCT", "LCT_TUNE_FRFT",
     "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
-    "LCT_FP32", "LCT_FP64",
+    "LCT_FP32", "LCT_FP64", "LCT_FP32_SPLITBF16",
 ]
 
 
@@ -135,7 +135,7 @@ def lct_plan_destroy(plan: Plan) -> None:
 
 def _plan_io(plan: Plan, x: torch.Tensor, out):
     _check_data(x, "x")
-    if _prec_of(x) != plan.precision:
+    if _dtype_of(plan.precision) != x.dtype:
         raise TypeError("input dtype does not match the plan's precision")
     batch = _batch_of(x, plan.N)
     return batch, _out_like(x, out)
@@ -163,9 +163,20 @@ def _check_params(P: torch.Tensor, batch: int, width: int, name: str) -> None:
         raise ValueError(f"{name} must hold {batch} x {width} values")
 
 
-def lct_exec_many(x: torch.Tensor, M4: torch.Tensor, out=None, stream=None) -> torch.Tensor:
-    _check_data(x, "x")
+def _prec_for(x: torch.Tensor, precision) -> int:
+    """The data type fixes FP32 or FP64; complex64 data may also ask for
+    LCT_FP32_SPLITBF16 (radix-16 stages on the matrix cores)."""
     prec = _prec_of(x)
+    if precision is None or precision == prec:
+        return prec
+    if precision == LCT_FP32_SPLITBF16 and prec == LCT_FP32:
+        return LCT_FP32_SPLITBF16
+    raise TypeError(f"precision {precision} does not match data of dtype {x.dtype}")
+
+
+def lct_exec_many(x: torch.Tensor, M4: torch.Tensor, out=None, stream=None, precision=None) -> torch.Tensor:
+    _check_data(x, "x")
+    prec = _prec_for(x, precision)
     N = x.shape[-1]
     batch = _batch_of(x, N)
     _check_params(M4, batch, 4, "M4")
@@ -176,9 +187,10 @@ def lct_exec_many(x: torch.Tensor, M4: torch.Tensor, out=None, stream=None) -> t
     return out
 
 
-def lct_exec_many_adjoint(g: torch.Tensor, M4: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+def lct_exec_many_adjoint(g: torch.Tensor, M4: torch.Tensor, out=None, stream=None,
+                          precision=None) -> torch.Tensor:
     _check_data(g, "g")
-    prec = _prec_of(g)
+    prec = _prec_for(g, precision)
     N = g.shape[-1]
     batch = _batch_of(g, N)
     _check_params(M4, batch, 4, "M4")

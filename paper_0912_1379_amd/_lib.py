@@ -24,6 +24,7 @@ LCT_ERR_UNSUPPORTED = -7
 
 LCT_FP32 = 0
 LCT_FP64 = 1
+LCT_FP32_SPLITBF16 = 2
 
 LCT_TUNE_LCT = 0
 LCT_TUNE_FRFT = 1

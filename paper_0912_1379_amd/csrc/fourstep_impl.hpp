@@ -20,7 +20,7 @@ namespace lctk {
 // Lanes run over the columns fastest, so every load instruction reads C
 // consecutive samples of a row; the results go through LDS once more so that
 // every store writes consecutive k1 of one transposed row.
-template <typename R, int E, int MODE>
+template <typename R, int E, int MODE, bool MF = false>
 __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FsArgs args)
 {
@@ -70,7 +70,10 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
     }
 
     C<R> *lds = smem + (size_t)sl * lds_elems(N1);
-    fft_lds<E>(v, lds, t, T1, args.sc1);
+    if constexpr (MF)
+        fft_lds_mfma(v, smem, sl, t, T1, N1, lds_elems(N1), args.sc1);
+    else
+        fft_lds<E>(v, lds, t, T1, args.sc1);
 
     // twiddle W_N^(n2 k1), k1 = t + T1 e: turns -(n2 t + e n2 T1) / N, the two
     // integer products reduced exactly modulo N
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
 
 // Pass 2.  Work-group: one signal, RR consecutive k1; lanes run over k1
 // fastest, so loads and stores both touch RR consecutive samples per row.
-template <typename R, int E, int MODE>
+template <typename R, int E, int MODE, bool MF = false>
 __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename Vec<R>::T *__restrict__ out,
                                                                        FsArgs args)
 {
@@ -139,7 +142,10 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
     const R mag = (R)k.amp_mag;
 
     C<R> *lds = smem + (size_t)r * lds_elems(N2);
-    fft_lds<E>(v, lds, t, T2, args.sc2);
+    if constexpr (MF)
+        fft_lds_mfma(v, smem, r, t, T2, N2, lds_elems(N2), args.sc2);
+    else
+        fft_lds<E>(v, lds, t, T2, args.sc2);
 
     const ThreadChirp c = MODE == MODE_FWD
                               ? seq_chirp(k.post_hi, k.post_lo, true, k1 + N1 * t, N1 * T2, N, inv2N, k.amp_turns)
@@ -155,10 +161,10 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
     }
 }
 
-template <typename R, int E>
+template <typename R, int E, bool MF = false>
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD> : k_fs1<R, E, MODE_ADJ>;
+    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF> : k_fs1<R, E, MODE_ADJ, MF>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -169,10 +175,10 @@ inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int n
     return hipGetLastError();
 }
 
-template <typename R, int E>
+template <typename R, int E, bool MF = false>
 inline hipError_t launch_fs2_t(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD> : k_fs2<R, E, MODE_ADJ>;
+    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF> : k_fs2<R, E, MODE_ADJ, MF>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)

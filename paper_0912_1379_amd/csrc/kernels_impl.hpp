@@ -11,6 +11,7 @@
 
 #include "fft_core.hpp"
 #include "lct_params.hpp"
+#include "mfma_fft.hpp"
 
 namespace lctk {
 
@@ -92,8 +93,10 @@ __device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
 //   forward: load f, times pre-chirp; DFT; times post-chirp and amplitude.
 //   adjoint: L^H g = conj(pre (DFT(post conj(g)))) (the DFT matrix is symmetric).
 // ---------------------------------------------------------------------------
-template <typename R, int E, int NFIX, int MODE>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
+// MF: radix-16 stages on the matrix cores (FP32 data, E = 16, split-BF16
+// products; see mfma_fft.hpp).
+template <typename R, int E, int NFIX, int MODE, bool MF = false, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_lct(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, LctArgs args)
 {
     using V = typename Vec<R>::T;
@@ -167,10 +170,14 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct(
         }
     }
 
-    if constexpr (NFIX > 0)
+    if constexpr (MF) {
+        static_assert(E == 16 && sizeof(R) == 4 && NFIX == 0, "matrix-core stages: FP32, E = 16");
+        fft_lds_mfma(v, smem, sl, t, T, N, lds_elems(N), args.sc);
+    } else if constexpr (NFIX > 0) {
         fft_lds_fixed<E, NFIX>(v, lds, t);
-    else
+    } else {
         fft_lds<E>(v, lds, t, T, args.sc);
+    }
 
     if (live && !k.b0) {
         const ThreadChirp cout = MODE == MODE_FWD
@@ -379,11 +386,11 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frft(
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-template <typename R, int E, int NFIX>
+template <typename R, int E, int NFIX, bool MF = false, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
                                hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD> : k_lct<R, E, NFIX, MODE_ADJ>;
+    auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD, MF, LB> : k_lct<R, E, NFIX, MODE_ADJ, MF, LB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)

@@ -20,12 +20,12 @@ struct lct_plan_s {
 
 namespace {
 
-int fs_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
+int fs_run(int64_t N, bool fp64, bool mf, const double *M4, const LctConst *k, int mode, const void *in, void *out,
            int64_t batch, hipStream_t s)
 {
     if (in == out)
         return LCT_ERR_ARG; // pass 1 reads columns of `in` while writing rows of `out`
-    const FsTiling f = select_fs(LCT_TUNE_LCT, N, N, fp64);
+    const FsTiling f = mf ? mfma_fs(N) : select_fs(LCT_TUNE_LCT, N, N, fp64);
     if (!f.ok)
         return LCT_ERR_UNSUPPORTED;
     return fs_launch(f, N, fp64, M4, k, mode, in, out, batch, s);
@@ -51,7 +51,7 @@ int validate_M(double a, double b, double c, double d)
     return LCT_OK;
 }
 
-int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in, void *out,
+int lct_run(int64_t N, bool fp64, bool mf, const double *M4, const LctConst *k, int mode, const void *in, void *out,
             int64_t batch, hipStream_t s)
 {
     if (batch < 0)
@@ -64,8 +64,8 @@ int lct_run(int64_t N, bool fp64, const double *M4, const LctConst *k, int mode,
     if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
         return rc;
     if (N > single_pass_limit(fp64))
-        return fs_run(N, fp64, M4, k, mode, in, out, batch, s);
-    const Tiling tl = select_tiling(LCT_TUNE_LCT, N, N, fp64, 0);
+        return fs_run(N, fp64, mf, M4, k, mode, in, out, batch, s);
+    const Tiling tl = mf ? mfma_tiling(N) : select_tiling(LCT_TUNE_LCT, N, N, fp64, 0);
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;
     return lct_launch(tl, N, fp64, M4, k, mode, in, out, batch, s);
@@ -130,6 +130,8 @@ int lct_launch(const Tiling &tl, int64_t N, bool fp64, const double *M4, const L
     const int64_t nb = (batch + tl.S - 1) / tl.S;
     if (nb > INT32_MAX)
         return LCT_ERR_ARG;
+    if (tl.mf)
+        return hip_status(launch_lct_mf(in, out, a, (int)nb, tl.block, tl.lds, s));
     return hip_status(launch_lct(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
 }
 
@@ -155,10 +157,12 @@ int fs_launch(const FsTiling &f, int64_t N, bool fp64, const double *M4, const L
     const int64_t nb1 = batch * (f.N2 / f.C), nb2 = batch * (f.N1 / f.RR);
     if (nb1 > INT32_MAX || nb2 > INT32_MAX)
         return LCT_ERR_ARG;
-    hipError_t e = launch_fs1(fp64, f.E1, in, out, a, (int)nb1, f.bs1, f.lds1, s);
+    hipError_t e = f.mf1 ? launch_fs1_mf(in, out, a, (int)nb1, f.bs1, f.lds1, s)
+                         : launch_fs1(fp64, f.E1, in, out, a, (int)nb1, f.bs1, f.lds1, s);
     if (e != hipSuccess)
         return LCT_ERR_HIP;
-    return hip_status(launch_fs2(fp64, f.E2, out, a, (int)nb2, f.bs2, f.lds2, s));
+    return hip_status(f.mf2 ? launch_fs2_mf(out, a, (int)nb2, f.bs2, f.lds2, s)
+                            : launch_fs2(fp64, f.E2, out, a, (int)nb2, f.bs2, f.lds2, s));
 }
 
 int frft_sp_launch(const Tiling &tl, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
@@ -221,7 +225,7 @@ int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, d
     if (out == nullptr)
         return LCT_ERR_ARG;
     *out = nullptr;
-    if (prec != LCT_FP32 && prec != LCT_FP64)
+    if (prec != LCT_FP32 && prec != LCT_FP64 && prec != LCT_FP32_SPLITBF16)
         return LCT_ERR_ARG;
     if (!smooth235(N))
         return LCT_ERR_UNSUPPORTED_N;
@@ -255,7 +259,7 @@ int lct_exec(lct_plan p, const void *in, void *out, int64_t batch, hipStream_t s
 {
     if (!p)
         return LCT_ERR_ARG;
-    return lct_run(p->N, p->prec == LCT_FP64, nullptr, &p->k, 0, in, out, batch, stream);
+    return lct_run(p->N, p->prec == LCT_FP64, p->prec == LCT_FP32_SPLITBF16, nullptr, &p->k, 0, in, out, batch, stream);
 }
 
 int lct_exec_adjoint(lct_plan p, const void *g, void *out, int64_t batch, hipStream_t stream)
@@ -264,32 +268,34 @@ int lct_exec_adjoint(lct_plan p, const void *g, void *out, int64_t batch, hipStr
         return LCT_ERR_ARG;
     if (p->b == 0.0)
         return LCT_ERR_UNSUPPORTED;
-    return lct_run(p->N, p->prec == LCT_FP64, nullptr, &p->k, 1, g, out, batch, stream);
+    return lct_run(p->N, p->prec == LCT_FP64, p->prec == LCT_FP32_SPLITBF16, nullptr, &p->k, 1, g, out, batch, stream);
 }
 
 int lct_exec_many(int64_t N, lct_precision prec, const double *M4, const void *in, void *out, int64_t batch,
                   hipStream_t stream)
 {
-    if (prec != LCT_FP32 && prec != LCT_FP64)
+    if (prec != LCT_FP32 && prec != LCT_FP64 && prec != LCT_FP32_SPLITBF16)
         return LCT_ERR_ARG;
     if (batch > 0 && (M4 == nullptr || ((uintptr_t)M4) % 8))
         return LCT_ERR_ARG;
-    return lct_run(N, prec == LCT_FP64, M4, nullptr, 0, in, out, batch, stream);
+    return lct_run(N, prec == LCT_FP64, prec == LCT_FP32_SPLITBF16, M4, nullptr, 0, in, out, batch, stream);
 }
 
 int lct_exec_many_adjoint(int64_t N, lct_precision prec, const double *M4, const void *g, void *out, int64_t batch,
                           hipStream_t stream)
 {
-    if (prec != LCT_FP32 && prec != LCT_FP64)
+    if (prec != LCT_FP32 && prec != LCT_FP64 && prec != LCT_FP32_SPLITBF16)
         return LCT_ERR_ARG;
     if (batch > 0 && (M4 == nullptr || ((uintptr_t)M4) % 8))
         return LCT_ERR_ARG;
-    return lct_run(N, prec == LCT_FP64, M4, nullptr, 1, g, out, batch, stream);
+    return lct_run(N, prec == LCT_FP64, prec == LCT_FP32_SPLITBF16, M4, nullptr, 1, g, out, batch, stream);
 }
 
 int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const void *f, const void *g,
                         double *grad4, int64_t batch, hipStream_t stream)
 {
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
     if (prec != LCT_FP32 && prec != LCT_FP64)
         return LCT_ERR_ARG;
     if (batch < 0)
@@ -328,6 +334,8 @@ int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, i
 {
     if (!p)
         return LCT_ERR_ARG;
+    if (p->prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
     if (!isfinite(z_re) || !isfinite(z_im))
         return LCT_ERR_ARG;
     if (hypot(z_re, z_im) > 1.0 + 1e-12)
@@ -341,6 +349,8 @@ int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out
 {
     if (!p)
         return LCT_ERR_ARG;
+    if (p->prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
     if (!isfinite(z_re) || !isfinite(z_im))
         return LCT_ERR_ARG;
     if (hypot(z_re, z_im) > 1.0 + 1e-12)
@@ -359,6 +369,8 @@ size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch)
 int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out, int64_t batch,
                    hipStream_t stream)
 {
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
     if (prec != LCT_FP32 && prec != LCT_FP64)
         return LCT_ERR_ARG;
     if (batch > 0 && (Z2 == nullptr || ((uintptr_t)Z2) % 8))
@@ -369,6 +381,8 @@ int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *
 int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const void *in, void *out, int64_t batch,
                       void *ws, size_t ws_bytes, hipStream_t stream)
 {
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
     if (prec != LCT_FP32 && prec != LCT_FP64)
         return LCT_ERR_ARG;
     if (batch > 0 && (Z2 == nullptr || ((uintptr_t)Z2) % 8))

@@ -80,6 +80,11 @@ struct FrLArgs {
     FrConst k;
     Sched sc1, sc2;
 };
+// FP32 with the radix-16 stages on the matrix cores (E = 16 only).
+hipError_t launch_lct_mf(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
+                         hipStream_t s);
+hipError_t launch_fs1_mf(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s);
+hipError_t launch_fs2_mf(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s);
 hipError_t launch_frl1(bool fp64, int E, const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds,
                        hipStream_t s);
 hipError_t launch_frl2(bool fp64, int E, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t s);

@@ -234,6 +234,43 @@ FsTiling fs_of(int64_t N, bool fp64, int N1, int E1, int E2, int C, int RR, cons
 
 namespace {
 
+bool pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+} // namespace
+
+Tiling mfma_tiling(int64_t N)
+{
+    if (!pow2(N) || N < 256 || N > single_pass_limit(false))
+        return Tiling{};
+    const int T = (int)(N / 16);
+    const int S = T >= 256 ? 1 : 256 / T;
+    Tiling t = tiling_of(N, false, 16, S, greedy_sched(N, 16, 16, false), 0);
+    t.mf = t.ok && t.block % 64 == 0;
+    t.ok = t.mf;
+    return t;
+}
+
+FsTiling mfma_fs(int64_t N)
+{
+    if (!pow2(N) || N <= single_pass_limit(false) || N > MAX_N)
+        return FsTiling{};
+    int lg = 0;
+    while ((int64_t(1) << lg) < N)
+        ++lg;
+    const int64_t N1 = int64_t(1) << (lg / 2), N2 = N / N1;
+    const int C = pick_group((int)N1, (int)(N1 / 16), 16, (int)N2, false, 64);
+    const int RR = pick_group((int)N2, (int)(N2 / 16), 16, (int)N1, false, 64);
+    FsTiling f = fs_of(N, false, (int)N1, 16, 16, C, RR, greedy_sched(N1, 16, 16, false),
+                       greedy_sched(N2, 16, 16, false));
+    if (!f.ok)
+        return f;
+    f.mf1 = N1 % 256 == 0 && f.bs1 % 64 == 0;
+    f.mf2 = N2 % 256 == 0 && f.bs2 % 64 == 0;
+    return f;
+}
+
+namespace {
+
 FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap)
 {
     const int64_t N2 = N / N1;

@@ -201,7 +201,7 @@ int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t
     if (nsig < 0 || nsig > INT32_MAX || (nsig > 0 && h_desc == nullptr))
         return LCT_ERR_ARG;
     if (prec != LCT_FP32)
-        return prec == LCT_FP64 ? LCT_ERR_UNSUPPORTED : LCT_ERR_ARG;
+        return (prec == LCT_FP64 || prec == LCT_FP32_SPLITBF16) ? LCT_ERR_UNSUPPORTED : LCT_ERR_ARG;
 
     // validate and classify
     struct Key {

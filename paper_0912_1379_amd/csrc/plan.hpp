@@ -18,6 +18,7 @@ struct Tiling {
     size_t lds = 0;
     Sched sc{};
     bool ok = false;
+    bool mf = false; // radix-16 stages on the matrix cores
 };
 
 // Two-pass (four-step) geometry of a length N = N1 N2 DFT: pass 1 runs C
@@ -27,6 +28,7 @@ struct FsTiling {
     size_t lds1 = 0, lds2 = 0;
     Sched sc1{}, sc2{};
     bool ok = false;
+    bool mf1 = false, mf2 = false; // pass 1 / pass 2 radix-16 stages on the matrix cores
 };
 
 bool smooth235(int64_t N);
@@ -47,6 +49,13 @@ FsTiling default_fs(int64_t N, bool fp64);
 // the heuristic.  kind: LCT_TUNE_LCT or LCT_TUNE_FRFT.
 Tiling select_tiling(int kind, int64_t N, int64_t Nfft, bool fp64, size_t extra);
 FsTiling select_fs(int kind, int64_t N, int64_t Nfft, bool fp64);
+
+// Geometry of the split-BF16 matrix-core variant (FP32 data): N a power of
+// two from 256 to 2^24; E = 16, radix-16 stages first.  One pass up to
+// 16384 points, beyond that N = N1 N2 with N1 = 2^floor(log2(N) / 2); a
+// pass whose length is not a multiple of 256 runs on the vector units.
+Tiling mfma_tiling(int64_t N);
+FsTiling mfma_fs(int64_t N);
 
 // Enumerates the candidate geometries the autotuner times.
 void tiling_candidates(int64_t Nfft, bool fp64, bool frft, Tiling *out, int *n, int cap);
