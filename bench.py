@@ -175,6 +175,11 @@ def bench_large(args):
     x64 = x32.to(torch.complex128)
     M4 = torch.from_numpy(M).to("cuda")
     y32, y64 = torch.empty_like(x32), torch.empty_like(x64)
+    tuning = None
+    if not args.no_tune:
+        tuning = {"fp32": lct.lct_autotune(N, lct.LCT_FP32, "lct", batch=B),
+                  "fp64": lct.lct_autotune(N, lct.LCT_FP64, "lct", batch=B)}
+        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
     ms, ms_kernel, wall = time_launches(lambda: lct.lct_exec_many(x32, M4, out=y32), args.steps, args.warmup)
     ms64, ms64_kernel, _ = time_launches(lambda: lct.lct_exec_many(x64, M4, out=y64), max(5, args.steps // 2), 2)
     ysp = torch.empty_like(x32)
@@ -196,6 +201,8 @@ def bench_large(args):
         "wall_s_timed": wall,
         "fp64_path": {"ms_per_step": ms64, "kernel_ms": ms64_kernel, "fp32_speedup": ms64 / ms},
         "splitbf16_path": {"ms_per_step": mss, "kernel_ms": mss_kernel},
+        "tuning": tuning,
+        "geometry": {"fp32": lct.lct_tune_get(N, lct.LCT_FP32, "lct"), "fp64": lct.lct_tune_get(N, lct.LCT_FP64, "lct")},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -324,6 +324,20 @@ template <int RAD> __device__ __forceinline__ void twiddles(double t0, C<double>
     twiddle_powers<RAD>(cis_turns(t0), w);
 }
 
+// Work-groups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remapping block i to logical index (i mod 8) * (n / 8) + i / 8 gives
+// every XCD a contiguous range of logical tiles, so neighbouring tiles, which
+// share cache lines, meet in one L2.  A bijection on the first 8 floor(n / 8)
+// blocks, the identity on the rest.  Placement only: any mapping is correct.
+__device__ __forceinline__ int xcd_remap(int i, int n)
+{
+    constexpr int X = 8;
+    const int per = n / X;
+    if (i >= per * X)
+        return i;
+    return (i % X) * per + i / X;
+}
+
 // LDS index with one pad element every 16 (breaks power-of-two bank strides).
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 __host__ __device__ constexpr int lds_elems(int N) { return N + (N >> 4) + 1; }

@@ -29,8 +29,9 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
     const int N = args.N, N1 = args.N1, N2 = args.N2, Cc = args.C, T1 = args.T1;
     const int tiles = N2 / Cc;
-    const int64_t s = blockIdx.x / tiles;
-    const int n20 = (int)(blockIdx.x - s * tiles) * Cc;
+    const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int64_t s = blk / tiles;
+    const int n20 = (int)(blk - s * tiles) * Cc;
     const int tid = (int)threadIdx.x;
     const int sl = tid % Cc; // column slot
     const int t = tid / Cc;
@@ -114,8 +115,9 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
     const int N = args.N, N1 = args.N1, N2 = args.N2, RR = args.RR, T2 = args.T2;
     const int tiles = N1 / RR;
-    const int64_t s = blockIdx.x / tiles;
-    const int k10 = (int)(blockIdx.x - s * tiles) * RR;
+    const int blk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int64_t s = blk / tiles;
+    const int k10 = (int)(blk - s * tiles) * RR;
     const int tid = (int)threadIdx.x;
     const int r = tid % RR;
     const int t = tid / RR;

@@ -149,7 +149,8 @@ int choose_E(int64_t N, bool fp64, bool frft)
 
 // Columns (or rows) per four-step work-group: as many as keep >= 128-byte
 // row segments, about 256 threads, and fit LDS and the launch bound, capped
-// at `cap`.
+// at `cap_limit` (smaller groups trade row-segment length for more resident
+// work-groups per CU; neighbouring groups then share lines in one L2).
 int pick_group(int Nsub, int T, int E, int other, bool fp64, int cap_limit)
 {
     const size_t elem = fp64 ? 16 : 8;
@@ -361,7 +362,7 @@ void fs_candidates(int64_t Nfft, bool fp64, FsTiling *out, int *n, int cap)
             break;
         const int64_t N1 = sp.second, N2 = Nfft / N1;
         const int e1 = choose_E(N1, fp64, false), e2 = choose_E(N2, fp64, false);
-        for (int cap : {64, 32, 16})
+        for (int cap : {64, 32, 16, 8, 4})
             push(fs_for_split(Nfft, fp64, N1, e1, e2, cap));
         for (int E1 : E_WIDTHS)
             for (int E2 : E_WIDTHS) {
