@@ -243,6 +243,90 @@ def test_autograd_matches_oracle():
         assert np.abs(gm - gm_ref).max() <= 1e-9 * np.abs(gm_ref).max()
 
 
+def _intensity_loss(x, M4, I):
+    y = lct.lct(x, M4)
+    return ((y.abs() ** 2 - I) ** 2).sum()
+
+
+def test_autograd_finite_differences_fp64_n64():
+    """The fit's loss ||abs(L_M f)^2 - I||^2 at N = 64 in FP64: autograd's
+    gradients w.r.t. (a, b, d) and f against central finite differences of the
+    same GPU forward (c is tied to the others by ad - bc = 1, so it is moved
+    with them: c = (ad - 1)/b)."""
+    N, B = 64, 3
+    M, f = c1_inputs(N, B, 21)
+    I = torch.rand(B, N, dtype=torch.float64, device="cuda") * 0.05
+    x = dev(f, torch.complex128).requires_grad_(True)
+    M4 = dev(M, torch.float64).requires_grad_(True)
+    _intensity_loss(x, M4, I).backward()
+    gM = M4.grad.cpu().numpy()
+    gx = x.grad.cpu().numpy()
+
+    def loss_at(Mh, fh):
+        with torch.no_grad():
+            return float(_intensity_loss(dev(fh, torch.complex128), dev(Mh, torch.float64), I))
+
+    h = 1e-6
+    for s in range(B):
+        for q in (0, 1, 3):  # a, b, d (c follows from the constraint)
+            Mp, Mm = M.copy(), M.copy()
+            Mp[s, q] += h
+            Mm[s, q] -= h
+            for Mx in (Mp, Mm):
+                Mx[s, 2] = (Mx[s, 0] * Mx[s, 3] - 1.0) / Mx[s, 1]
+            fd = (loss_at(Mp, f) - loss_at(Mm, f)) / (2 * h)
+            # the chain through c: dl/dq + dl/dc * dc/dq
+            a, b, c, d = M[s]
+            dc = {0: d / b, 1: -(a * d - 1.0) / b ** 2, 3: a / b}[q]
+            an = gM[s, q] + gM[s, 2] * dc
+            assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (s, q, an, fd)
+        g = np.random.default_rng(s)
+        for _ in range(3):
+            k = int(g.integers(N))
+            for dirn, part in ((1.0, "re"), (1j, "im")):
+                fp, fm = f.copy(), f.copy()
+                fp[s, k] += h * dirn
+                fm[s, k] -= h * dirn
+                fd = (loss_at(M, fp) - loss_at(M, fm)) / (2 * h)
+                an = gx[s, k].real if part == "re" else gx[s, k].imag
+                assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (s, k, part, an, fd)
+
+
+def test_fit_recovers_hidden_matrix_intensity():
+    """A few Adam steps on ||abs(L_M f)^2 - I*||^2 (I* from a hidden M*)
+    reduce the loss and move (a, b) toward M*; d and c do not enter the
+    intensity for b != 0 beyond the constraint."""
+    N, B = 2048, 8
+    g = np.random.default_rng(31)
+    Mstar = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    f = dev(workloads.chirped_gaussians(oracle.nodes(N), gp), torch.complex64)
+    with torch.no_grad():
+        target = lct.lct(f, dev(Mstar, torch.float64)).abs() ** 2
+    M0 = Mstar.copy()
+    M0[:, 0] += 0.05
+    M0[:, 2] = (M0[:, 0] * M0[:, 3] - 1) / M0[:, 1]
+    P = dev(M0[:, [0, 1, 3]], torch.float64).requires_grad_(True)
+    opt = torch.optim.Adam([P], lr=5e-3)
+
+    def full(P):
+        a, b, d = P[:, 0], P[:, 1], P[:, 2]
+        return torch.stack([a, b, (a * d - 1) / b, d], dim=1)
+
+    losses = []
+    for _ in range(60):
+        opt.zero_grad()
+        loss = ((lct.lct(f, full(P)).abs() ** 2 - target) ** 2).sum()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    print("fit losses", losses[::10])
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
+    err0 = np.abs(M0[:, 0] - Mstar[:, 0]).mean()
+    err1 = np.abs(P.detach().cpu().numpy()[:, 0] - Mstar[:, 0]).mean()
+    assert err1 < err0, (err0, err1)
+
+
 def test_error_codes_on_device_buffers():
     x = torch.zeros(2, 64, dtype=torch.complex64, device="cuda")
     M4 = torch.zeros(2, 4, dtype=torch.float64, device="cuda")
