@@ -510,6 +510,18 @@ __host__ __device__ constexpr int fixed_nstages(int N, int E)
     return s;
 }
 
+// True when a runtime schedule is the compile-time one of (N, E), so that a
+// kernel instantiated for that length can run it.
+__host__ __device__ inline bool is_fixed_sched(const Sched &sc, int N, int E)
+{
+    if (sc.nst != fixed_nstages(N, E))
+        return false;
+    for (int s = 0; s < sc.nst; ++s)
+        if (sc.rad[s] != fixed_radix(N, E, s))
+            return false;
+    return true;
+}
+
 // In-LDS forward FFT of the register values v (positions t + T e), in place.
 // All threads of the work-group must call it (it contains barriers).  On
 // return v[e] holds output position t + T e.  The LDS buffer is free again

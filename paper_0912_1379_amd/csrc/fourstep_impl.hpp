@@ -20,7 +20,10 @@ namespace lctk {
 // Lanes run over the columns fastest, so every load instruction reads C
 // consecutive samples of a row; the results go through LDS once more so that
 // every store writes consecutive k1 of one transposed row.
-template <typename R, int E, int MODE, bool MF = false>
+// NFIX > 0: the column length N1 = NFIX with its compile-time radix schedule
+// (constant strides and radices keep the register demand low enough for the
+// 1024-thread launch bound without spills).
+template <typename R, int E, int MODE, bool MF = false, int NFIX = 0>
 __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FsArgs args)
 {
@@ -73,6 +76,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
     C<R> *lds = smem + (size_t)sl * lds_elems(N1);
     if constexpr (MF)
         fft_lds_mfma(v, smem, sl, t, T1, N1, lds_elems(N1), args.sc1);
+    else if constexpr (NFIX > 0)
+        fft_lds_fixed<E, NFIX>(v, lds, t);
     else
         fft_lds<E>(v, lds, t, T1, args.sc1);
 
@@ -106,7 +111,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
 
 // Pass 2.  Work-group: one signal, RR consecutive k1; lanes run over k1
 // fastest, so loads and stores both touch RR consecutive samples per row.
-template <typename R, int E, int MODE, bool MF = false>
+// NFIX > 0: the row length N2 = NFIX with its compile-time radix schedule.
+template <typename R, int E, int MODE, bool MF = false, int NFIX = 0>
 __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename Vec<R>::T *__restrict__ out,
                                                                        FsArgs args)
 {
@@ -146,6 +152,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
     C<R> *lds = smem + (size_t)r * lds_elems(N2);
     if constexpr (MF)
         fft_lds_mfma(v, smem, r, t, T2, N2, lds_elems(N2), args.sc2);
+    else if constexpr (NFIX > 0)
+        fft_lds_fixed<E, NFIX>(v, lds, t);
     else
         fft_lds<E>(v, lds, t, T2, args.sc2);
 
@@ -163,10 +171,14 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
     }
 }
 
-template <typename R, int E, bool MF = false>
+// Sub-lengths with compile-time schedules (E = 16): the four-step splits of
+// 2^16 .. 2^24.
+#define LCT_FS_FIXED_LIST(X) X(256) X(512) X(1024) X(2048) X(4096)
+
+template <typename R, int E, bool MF = false, int NFIX = 0>
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF> : k_fs1<R, E, MODE_ADJ, MF>;
+    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF, NFIX> : k_fs1<R, E, MODE_ADJ, MF, NFIX>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -177,10 +189,10 @@ inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int n
     return hipGetLastError();
 }
 
-template <typename R, int E, bool MF = false>
+template <typename R, int E, bool MF = false, int NFIX = 0>
 inline hipError_t launch_fs2_t(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF> : k_fs2<R, E, MODE_ADJ, MF>;
+    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF, NFIX> : k_fs2<R, E, MODE_ADJ, MF, NFIX>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)

@@ -5,6 +5,17 @@ namespace lctk {
 
 hipError_t dispatch_fs2_f64(int E, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
+    if (E == 16 && is_fixed_sched(a.sc2, a.N2, 16)) {
+        switch (a.N2) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_fs2_t<double, 16, false, n>(out, a, nb, bs, lds, s);
+            LCT_FS_FIXED_LIST(X)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

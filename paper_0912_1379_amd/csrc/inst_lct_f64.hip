@@ -7,10 +7,20 @@ namespace lctk {
 hipError_t dispatch_lct_f64(int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,
                             hipStream_t s)
 {
-    // compile-time schedule for the geometry E=16 S=1 rad=16.16.16 of N = 4096
-    // (that kernel assumes one signal per work-group)
-    if (a.N == 4096 && E == 16 && a.S == 1 && a.sc.nst == 3 && a.sc.rad[0] == 16 && a.sc.rad[1] == 16 && a.sc.rad[2] == 16)
-        return launch_lct_t<double, 16, 4096>(in, out, a, nb, bs, lds, s);
+    // compile-time radix schedules (E = 16) for the common lengths; the
+    // instantiations with N / 16 >= 256 threads assume one signal per
+    // work-group
+    if (E == 16 && is_fixed_sched(a.sc, a.N, 16) && (a.N / 16 < 256 || a.S == 1)) {
+        switch (a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_lct_t<double, 16, n>(in, out, a, nb, bs, lds, s);
+            X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \
