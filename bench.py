@@ -239,6 +239,55 @@ def bench_large(args):
     return out
 
 
+def bench_frft(args):
+    """Batched same-grid fractional transform: 4096 signals x N = 4096
+    complex64, one order z = r e^{-i theta} per signal (r ~ U(0.5, 1)),
+    chirped-Gaussian inputs; one step = one frft_exec_many call (length-8192
+    convolution in LDS per signal)."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    B, N = args.signals, args.N
+    g = workloads.rng(2, 1)
+    z = workloads.frft_orders(B, g)
+    gp = workloads.gaussian_params(B, g)
+    xn, _ = lct.lct_nodes(N, 1.0)
+    x = torch.from_numpy(workloads.chirped_gaussians(xn, gp)).to("cuda").to(torch.complex64)
+    Z2 = torch.from_numpy(np.stack([z.real, z.imag], axis=1)).to("cuda")
+    y = torch.empty_like(x)
+    tuning = None if args.no_tune else lct.lct_autotune(N, lct.LCT_FP32, "frft", batch=B)
+    ms, ms_kernel, wall = time_launches(lambda: lct.frft_exec_many(x, Z2, out=y), args.steps, args.warmup)
+    samples = B * N
+    gbps = 16.0 * samples / (ms_kernel * 1e-3) / 1e9
+    out = {
+        "metric": "complex samples/s, batched same-grid fractional transform",
+        "value": samples / (ms * 1e-3), "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"fractional transform, {B} signals x N={N} complex64, one order per signal",
+                   "signals": B, "N": N, "geometry": lct.lct_tune_get(N, lct.LCT_FP32, "frft")},
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_frft (FP32)",
+                     "kernel_ms": ms_kernel, "algorithmic_bytes_per_launch": 16.0 * samples},
+        "wall_s_timed": wall, "tuning": tuning,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        errs = []
+        t0 = time.perf_counter()
+        for s in range(3):
+            fin = x[s].cpu().numpy().astype(np.complex128)
+            ref = oracle.frft(fin, complex(z[s]))
+            errs.append(float(np.linalg.norm(y[s].cpu().numpy() - ref) / np.linalg.norm(ref)))
+        el = time.perf_counter() - t0
+        out["rel_l2"] = {"max": max(errs), "signals": 3}
+        out["cpu_baseline"] = {"value": 3 * N / el, "unit": "complex samples/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"3 whole signals (dense N={N} sums), {el:.1f} s"}
+    return out
+
+
 def bench_fit(args):
     """Differentiable LCT fit: 256 signals x N = 2048 complex64, loss
     ||abs(LCT_M(f))^2 - I_target||^2 with I_target from a hidden matrix; one
@@ -290,9 +339,9 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 matrix-core variant")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
-    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit"], default="batched",
+    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft"], default="batched",
                     help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
-                         "large: 16 x 2^20; fit: autograd step at 256 x 2048")
+                         "large: 16 x 2^20; fit: autograd step at 256 x 2048; frft: 4096 x N=4096 fractional")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -302,7 +351,7 @@ def main():
         sys.exit(2)
 
     if args.workload != "batched":
-        fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit}[args.workload]
+        fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit, "frft": bench_frft}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

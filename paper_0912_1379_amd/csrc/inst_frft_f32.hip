@@ -7,6 +7,20 @@ namespace lctk {
 hipError_t dispatch_frft_f32(int E, const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds,
                              hipStream_t s)
 {
+    // compile-time radix schedules (E = 16) for the common convolution lengths
+    if (E == 16 && is_fixed_sched(a.sc, 2 * a.N, 16)) {
+        switch (2 * a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        if (bs <= tight_bound(n))                                                                                    \
+            return launch_frft_t<float, 16, n, tight_bound(n)>(in, out, a, nb, bs, lds, s);                          \
+        return launch_frft_t<float, 16, n>(in, out, a, nb, bs, lds, s);
+            X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

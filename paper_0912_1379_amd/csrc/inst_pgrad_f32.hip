@@ -7,6 +7,20 @@ namespace lctk {
 hipError_t dispatch_pgrad_f32(int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,
                               int bs, size_t lds, hipStream_t s)
 {
+    // compile-time radix schedules (E = 16) for the common lengths
+    if (E == 16 && is_fixed_sched(a.sc, a.N, 16)) {
+        switch (a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        if (bs <= tight_bound(n))                                                                                    \
+            return launch_pgrad_t<float, 16, n, tight_bound(n)>(f, g, grad4, a, nb, bs, lds, s);                     \
+        return launch_pgrad_t<float, 16, n>(f, g, grad4, a, nb, bs, lds, s);
+            X(256) X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

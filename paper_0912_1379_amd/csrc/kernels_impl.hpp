@@ -201,16 +201,16 @@ __global__ __launch_bounds__(LB) void k_lct(
 // S_n = Re sum conj(g) i (n_j^2 / N) G, combined into
 // dl/da = S_H, dl/db = -S_G/(2b) - (a/b) S_H + d S_n, dl/dc = 0, dl/dd = b S_n.
 // ---------------------------------------------------------------------------
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_pgrad(
+template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_lct_pgrad(
     const typename Vec<R>::T *__restrict__ f, const typename Vec<R>::T *__restrict__ g,
     double *__restrict__ grad4, LctArgs args)
 {
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
-    const int N = args.N;
-    const int T = args.T;
+    const int N = NFIX > 0 ? NFIX : args.N;
+    const int T = NFIX > 0 ? NFIX / E : args.T;
     const Sched &sc = args.sc;
     const int sl = (int)threadIdx.x / T;
     const int t = (int)threadIdx.x - sl * T;
@@ -245,7 +245,10 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_pgrad(
                 x = cmul_pi(cscale(x, (R)(qscale * nsq(i, N))));
             v[e] = x;
         }
-        fft_lds<E>(v, lds, t, T, sc);
+        if constexpr (NFIX > 0)
+            fft_lds_fixed<E, NFIX>(v, lds, t);
+        else
+            fft_lds<E>(v, lds, t, T, sc);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = t + T * e;
@@ -307,16 +310,33 @@ __device__ __forceinline__ C<R> gauss_chirp(double mag_per, double ph_hi, double
     return cscale(c, s);
 }
 
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frft(
+// Launch bound of a fixed-length instantiation (E = 16): the work-group of the
+// default geometry, max(256, length / 16) threads, so that the register
+// budget is not cut to what 1024 threads would allow.
+constexpr int tight_bound(int n) { return n / 16 > 256 ? n / 16 : 256; }
+
+// The in-LDS FFT with a compile-time schedule when NF > 0, else the runtime one.
+template <typename R, int E, int NF>
+__device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const Sched &sc)
+{
+    if constexpr (NF > 0)
+        fft_lds_fixed<E, NF>(v, lds, t);
+    else
+        fft_lds<E>(v, lds, t, T, sc);
+}
+
+// LFIX > 0: the convolution length L = 2N = LFIX with its compile-time radix
+// schedule.
+template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_frft(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FrArgs args)
 {
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
-    const int N = args.N;
+    const int N = LFIX > 0 ? LFIX / 2 : args.N;
     const int L = 2 * N;
-    const int T = args.T; // = L / E
+    const int T = LFIX > 0 ? LFIX / E : args.T; // = L / E
     const Sched &sc = args.sc;
     const int sl = (int)threadIdx.x / T;
     const int t = (int)threadIdx.x - sl * T;
@@ -349,7 +369,7 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frft(
         const double m2 = (double)m * (double)m;
         K[e] = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, m2);
     }
-    fft_lds<E>(K, lds, t, T, sc);
+    fft_any<R, E, LFIX>(K, lds, t, T, sc);
 
     // 2) data e^{-P x_k^2} f_k (reversed for Hankel), zero-padded to L
     C<R> v[E];
@@ -363,13 +383,13 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frft(
         }
         v[e] = x;
     }
-    fft_lds<E>(v, lds, t, T, sc);
+    fft_any<R, E, LFIX>(v, lds, t, T, sc);
 
     // 3) inverse DFT of the product: conj(FFT(conj(V K)))
 #pragma unroll
     for (int e = 0; e < E; ++e)
         v[e] = cconj(cmul(v[e], K[e]));
-    fft_lds<E>(v, lds, t, T, sc);
+    fft_any<R, E, LFIX>(v, lds, t, T, sc);
 
     if (live && !k.special) {
 #pragma unroll
@@ -401,11 +421,11 @@ inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int 
     return hipGetLastError();
 }
 
-template <typename R, int E>
+template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_pgrad_t(const void *f, const void *g, double *grad4, const LctArgs &a, int nblocks,
                                  int block, size_t lds, hipStream_t s)
 {
-    auto kern = k_lct_pgrad<R, E>;
+    auto kern = k_lct_pgrad<R, E, NFIX, LB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -416,11 +436,11 @@ inline hipError_t launch_pgrad_t(const void *f, const void *g, double *grad4, co
     return hipGetLastError();
 }
 
-template <typename R, int E>
+template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int nblocks, int block, size_t lds,
                                 hipStream_t s)
 {
-    auto kern = k_frft<R, E>;
+    auto kern = k_frft<R, E, LFIX, LB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
