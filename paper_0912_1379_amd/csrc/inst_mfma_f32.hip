@@ -1,12 +1,17 @@
 // inst_mfma_f32.hip - FP32 kernels whose radix-16 stages run on the matrix
 // cores (split-BF16 products with FP32 accumulation).
 #include "fourstep_impl.hpp"
+#include "mfma_lct_impl.hpp"
 
 namespace lctk {
 
 hipError_t launch_lct_mf(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
                          hipStream_t s)
 {
+    // N = 4096 = 16^3: every stage on the matrix cores, HBM in and out of
+    // the first and last stage directly
+    if (a.N == 4096 && a.S == 1 && block == 256)
+        return launch_lct_mf4096_t(in, out, a, nblocks, lds, s);
     // a 256-thread bound leaves the register file to the one work-group size
     // of N <= 4096 (no spills); larger N need up to 1024 threads
     if (block <= 256)
