@@ -337,6 +337,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 matrix-core variant")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device-to-device copy reference")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
     ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft"], default="batched",
@@ -411,6 +412,17 @@ def main():
                  "kernel": "k_lct (FP32 data, radix-16 stages as split-BF16 MFMA)"}
         print(f"[bench] split-bf16: {mss * 1e3:.1f} us/step", file=sys.stderr, flush=True)
 
+    # device-to-device copy of the same bytes (128 MiB read + 128 MiB written):
+    # the practical streaming rate of this part, beside the 8 TB/s peak
+    hbm_copy = None
+    if not args.no_copy:
+        copy_ms, copy_kernel_ms, _ = time_launches(lambda: y32.copy_(x32), 20, 3)
+        hbm_copy = {"GBps": algo_bytes / (copy_kernel_ms * 1e-3) / 1e9, "bytes_per_launch": algo_bytes,
+                    "kernel_ms": copy_kernel_ms, "what": "torch copy_ of the 4096 x 4096 complex64 input"}
+        print(f"[bench] copy: {copy_kernel_ms * 1e3:.1f} us, {hbm_copy['GBps']:.0f} GB/s", file=sys.stderr,
+              flush=True)
+        lct.lct_exec_many(x32, M4, out=y32)  # restore the output the error check reads
+
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
@@ -441,6 +453,7 @@ def main():
         "wall_s_timed": wall,
         "fp64_path": fp64,
         "splitbf16_path": split,
+        "hbm_copy": hbm_copy,
         "tuning": tuning,
     }
 

@@ -165,8 +165,11 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
  * the device for execution; sizes, kinds and offsets must agree, the
  * parameters p may change between executions):
  *   offset  element offset of the signal in `in` and `out` (complex64)
- *   N       its length (2^p 3^q 5^r, at most 65536 for the fractional
- *           transform and the LCT alike in this build)
+ *   N       its length, of the form 2^k, 3 2^k or 5 2^k; short signals run
+ *           in LDS, long ones as a four-step FFT inside one work-group whose
+ *           two factors (of N, or of 2N for the fractional transform) must
+ *           have that form too (up to N = 2^24 for the LCT); other lengths
+ *           give LCT_ERR_UNSUPPORTED
  *   kind    LCT_KIND_LCT: p = (a, b, c, d), ad - bc = 1;
  *           LCT_KIND_FRFT: p = (re z, im z, -, -), |z| <= 1
  * The plan validates the host descriptors, groups short signals of one length

@@ -580,3 +580,47 @@ def test_graph_capture_replays_match_eager():
         assert torch.equal(y, eager_y), r
         assert torch.equal(g, eager_g), r
         assert torch.equal(w, eager_w), r
+
+
+def test_maximum_sizes():
+    """N = 2^24 (the largest supported length) for the LCT in FP32 and
+    N = 2^22 for the fractional transform (length-2^23 convolution through
+    its workspace), one signal each, on rows where the output has energy."""
+    for N, kind in ((1 << 24, "lct"), (1 << 22, "frft")):
+        g = np.random.default_rng(N)
+        gp = workloads.gaussian_params(1, g)
+        f = workloads.chirped_gaussians(oracle.nodes(N), gp)
+        x = dev(f, torch.complex64)
+        fin = x.cpu().numpy().astype(np.complex128)[0]
+        if kind == "lct":
+            M = workloads.sl2_params(1, g)
+            y = lct.lct_exec_many(x, dev(M, torch.float64)).cpu().numpy()[0]
+            rows = peak_rows(M[0], gp[0], N, 24, 1)
+            ref = oracle.lct(fin, *M[0], rows=rows)
+        else:
+            z = 0.7 * np.exp(-0.9j)
+            y = lct.frft_exec_many(x, dev(np.array([[z.real, z.imag]]), torch.float64)).cpu().numpy()[0]
+            rows = frft_peak_rows(gp[0], z, N, 24, 1)
+            ref = oracle.frft(fin, z, rows=rows)
+        assert rel_rows(y[rows], ref)[0] <= 2e-5, (N, kind)
+
+
+def test_ragged_long_signals_beyond_65536():
+    """Ragged items up to N = 2^20 (LCT) and 2^19 (fractional transform):
+    four-step inside one work-group with sub-lengths up to 4096."""
+    sizes = [1 << 20, 1 << 19, 3 * (1 << 15), 5 * (1 << 14), 4096, 1 << 18]
+    N, kinds, M, z, gp, desc, x = ragged_case(len(sizes), 53, sizes=sizes)
+    plan = lct.RaggedPlan(desc)
+    xd = dev(x, torch.complex64)
+    y = lct.lct_exec_ragged(plan, xd).cpu().numpy()
+    check_ragged(N, kinds, M, z, gp, desc, xd.cpu().numpy().astype(np.complex128), y, range(len(N)), nrow=24)
+
+
+def test_ragged_plan_rejects_unsupported_lengths():
+    for n, code in ((3 ** 10, lct.LCT_ERR_UNSUPPORTED), (7 * 64, lct.LCT_ERR_UNSUPPORTED_N),
+                    ((1 << 24) * 2, lct.LCT_ERR_UNSUPPORTED_N)):
+        desc = lct.make_descriptors(np.array([n]), np.array([lct.LCT_KIND_LCT]),
+                                    np.array([[1.0, 1.0, 0.0, 1.0]]))
+        with pytest.raises(lct.LctError) as ei:
+            lct.RaggedPlan(desc)
+        assert ei.value.code == code, (n, ei.value.code)
