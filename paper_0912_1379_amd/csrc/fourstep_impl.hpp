@@ -23,8 +23,8 @@ namespace lctk {
 // NFIX > 0: the column length N1 = NFIX with its compile-time radix schedule
 // (constant strides and radices keep the register demand low enough for the
 // 1024-thread launch bound without spills).
-template <typename R, int E, int MODE, bool MF = false, int NFIX = 0>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
+template <typename R, int E, int MODE, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_fs1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FsArgs args)
 {
     using V = typename Vec<R>::T;
@@ -112,8 +112,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs1(
 // Pass 2.  Work-group: one signal, RR consecutive k1; lanes run over k1
 // fastest, so loads and stores both touch RR consecutive samples per row.
 // NFIX > 0: the row length N2 = NFIX with its compile-time radix schedule.
-template <typename R, int E, int MODE, bool MF = false, int NFIX = 0>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename Vec<R>::T *__restrict__ out,
+template <typename R, int E, int MODE, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_fs2(typename Vec<R>::T *__restrict__ out,
                                                                        FsArgs args)
 {
     using V = typename Vec<R>::T;
@@ -175,10 +175,10 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_fs2(typename V
 // 2^16 .. 2^24.
 #define LCT_FS_FIXED_LIST(X) X(256) X(512) X(1024) X(2048) X(4096)
 
-template <typename R, int E, bool MF = false, int NFIX = 0>
+template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF, NFIX> : k_fs1<R, E, MODE_ADJ, MF, NFIX>;
+    auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF, NFIX, LB> : k_fs1<R, E, MODE_ADJ, MF, NFIX, LB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -189,10 +189,10 @@ inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int n
     return hipGetLastError();
 }
 
-template <typename R, int E, bool MF = false, int NFIX = 0>
+template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_fs2_t(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF, NFIX> : k_fs2<R, E, MODE_ADJ, MF, NFIX>;
+    auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF, NFIX, LB> : k_fs2<R, E, MODE_ADJ, MF, NFIX, LB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)

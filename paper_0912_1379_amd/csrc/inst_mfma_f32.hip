@@ -19,13 +19,19 @@ hipError_t launch_lct_mf(const void *in, void *out, const LctArgs &a, int nblock
     return launch_lct_t<float, 16, 0, true>(in, out, a, nblocks, block, lds, s);
 }
 
+// The four-step passes run 256-thread work-groups (16 lengths' worth of
+// threads); the 256-thread bound leaves them the register file.
 hipError_t launch_fs1_mf(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
+    if (bs <= 256)
+        return launch_fs1_t<float, 16, true, 0, 256>(in, out, a, nb, bs, lds, s);
     return launch_fs1_t<float, 16, true>(in, out, a, nb, bs, lds, s);
 }
 
 hipError_t launch_fs2_mf(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
+    if (bs <= 256)
+        return launch_fs2_t<float, 16, true, 0, 256>(out, a, nb, bs, lds, s);
     return launch_fs2_t<float, 16, true>(out, a, nb, bs, lds, s);
 }
 

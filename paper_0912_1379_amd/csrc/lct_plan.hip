@@ -259,8 +259,10 @@ FsTiling mfma_fs(int64_t N)
     while ((int64_t(1) << lg) < N)
         ++lg;
     const int64_t N1 = int64_t(1) << (lg / 2), N2 = N / N1;
-    const int C = pick_group((int)N1, (int)(N1 / 16), 16, (int)N2, false, 64);
-    const int RR = pick_group((int)N2, (int)(N2 / 16), 16, (int)N1, false, 64);
+    // 256-thread work-groups: 256 / (N1 / 16) columns, 256 / (N2 / 16) rows
+    // (neighbouring tiles share an L2 through the XCD-aware tile order)
+    const int C = (int)std::max<int64_t>(1, 256 / (N1 / 16));
+    const int RR = (int)std::max<int64_t>(1, 256 / (N2 / 16));
     FsTiling f = fs_of(N, false, (int)N1, 16, 16, C, RR, greedy_sched(N1, 16, 16, false),
                        greedy_sched(N2, 16, 16, false));
     if (!f.ok)
