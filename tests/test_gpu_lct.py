@@ -624,3 +624,33 @@ def test_ragged_plan_rejects_unsupported_lengths():
         with pytest.raises(lct.LctError) as ei:
             lct.RaggedPlan(desc)
         assert ei.value.code == code, (n, ei.value.code)
+
+
+def test_large_precision_sweep_with_noise():
+    """16 x 2^20 chirped Gaussians plus white complex noise (std 1e-3), FP64,
+    FP32 and split-BF16 (the large-N precision sweep): 64 sampled outputs
+    per signal, 1024 in all, against the oracle's FP64 rows."""
+    N, B, nrow = 1 << 20, 16, 64
+    g = np.random.default_rng(2020)
+    M = workloads.sl2_params(B, g)
+    gp = workloads.gaussian_params(B, g)
+    f = workloads.chirped_gaussians(oracle.nodes(N), gp) + workloads.white_noise((B, N), g)
+    x32 = dev(f, torch.complex64)
+    M4 = dev(M, torch.float64)
+    outs = {
+        "fp32": (lct.lct_exec_many(x32, M4).cpu().numpy(), x32.cpu().numpy().astype(np.complex128), 2e-5),
+        "split": (lct.lct_exec_many(x32, M4, precision=lct.LCT_FP32_SPLITBF16).cpu().numpy(),
+                  x32.cpu().numpy().astype(np.complex128), 2e-4),
+    }
+    x64 = dev(f, torch.complex128)
+    outs["fp64"] = (lct.lct_exec_many(x64, M4).cpu().numpy(), f, 1e-12)
+    del x64
+    for s in range(B):
+        rows = peak_rows(M[s], gp[s], N, nrow, s)
+        ref32 = oracle.lct(outs["fp32"][1][s], *M[s], rows=rows)  # FP32 and split-BF16 share the cast input
+        for name, (y, fin, tol) in outs.items():
+            if name == "fp64" and s >= 4:
+                continue  # FP64 rows for 4 signals (its oracle rows are the costly part)
+            ref = ref32 if name != "fp64" else oracle.lct(fin[s], *M[s], rows=rows)
+            e = rel_rows(y[s][rows], ref)[0]
+            assert e <= tol, (name, s, e)
