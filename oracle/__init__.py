@@ -15,7 +15,10 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             §1; pinned by eq. (exa1) at the two parameter sets
                             of §4, the Hermite-Gauss closed form, unitarity,
                             numpy's FFT for a=d=0, b=1, the composition law
-                            and mpmath brute force.
+                            and mpmath brute force.  ``scale=s`` takes the
+                            samples on s x_k (outputs on 4 b x_j / (pi s));
+                            pinned by the Gaussian closed form on scaled grids
+                            and by chains of two transforms.
 ``lct_adjoint``             conjugate transpose of the same matrix; pinned by
                             the inner-product identity and unitarity.
 ``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d);
@@ -59,6 +62,8 @@ def _load():
     lib.oracle_nodes.argtypes = [i64, _dp]
     lib.oracle_lct_rows.argtypes = [i64, d, d, d, d, _dp, _i64p, i64, _dp]
     lib.oracle_lct_rows.restype = ctypes.c_int
+    lib.oracle_lct_rows_scaled.argtypes = [i64, d, d, d, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_lct_rows_scaled.restype = ctypes.c_int
     lib.oracle_lct_adjoint.argtypes = [i64, d, d, d, d, _dp, _dp]
     lib.oracle_lct_adjoint.restype = ctypes.c_int
     lib.oracle_lct_param_grad.argtypes = [i64, d, d, d, d, _dp, _dp, _dp]
@@ -93,22 +98,25 @@ def nodes(N: int) -> np.ndarray:
     return x
 
 
-def output_nodes(N: int, b: float, d: float = 1.0) -> np.ndarray:
-    """Output nodes: y_j = 4 b x_j / pi (Algorithm) for b != 0, x_j / d for b = 0."""
+def output_nodes(N: int, b: float, d: float = 1.0, scale: float = 1.0) -> np.ndarray:
+    """Output nodes for samples on the input grid scale * x_k:
+    y_j = 4 b x_j / (pi scale) for b != 0 (the Algorithm's y_j at scale 1),
+    scale * x_j / d for b = 0."""
     x = nodes(N)
     if b == 0.0:
-        return x / d
-    return 4.0 * b * x / np.pi
+        return scale * x / d
+    return 4.0 * b * x / (np.pi * scale)
 
 
-def lct(f, a: float, b: float, c: float, d: float, rows=None) -> np.ndarray:
-    """Discrete LCT (O1) of the length-N sample vector f (complex).
+def lct(f, a: float, b: float, c: float, d: float, rows=None, scale: float = 1.0) -> np.ndarray:
+    """Discrete LCT (O1) of the length-N sample vector f (complex), sampled on
+    the input grid scale * x_k.
 
     ``f`` may be 1-D (one signal) or 2-D (signals x N, all with the same M).
     ``rows`` selects output indices (default: all N)."""
     f = _cplx_in(f)
     if f.ndim == 2:
-        return np.stack([lct(fi, a, b, c, d, rows) for fi in f])
+        return np.stack([lct(fi, a, b, c, d, rows, scale) for fi in f])
     N = f.shape[0]
     if rows is None:
         r = None
@@ -117,9 +125,9 @@ def lct(f, a: float, b: float, c: float, d: float, rows=None) -> np.ndarray:
         r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
         nr = r.shape[0]
     out = np.empty(nr, dtype=np.complex128)
-    rc = _load().oracle_lct_rows(N, a, b, c, d, _ptr(f.view(np.float64)),
-                                 None if r is None else r.ctypes.data_as(_i64p), nr,
-                                 _ptr(out.view(np.float64)))
+    rc = _load().oracle_lct_rows_scaled(N, a, b, c, d, float(scale), _ptr(f.view(np.float64)),
+                                        None if r is None else r.ctypes.data_as(_i64p), nr,
+                                        _ptr(out.view(np.float64)))
     if rc != 0:
         raise ValueError(f"oracle_lct_rows failed ({rc})")
     return out

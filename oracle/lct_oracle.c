@@ -62,33 +62,40 @@ static long double complex inv_sqrt_2pi_i_b(long double b)
 }
 
 /*
- * O1: discrete LCT as the Riemann sum of the definition of §1,
- *   G_j = sum_k h (2 pi i b)^(-1/2) exp(i [a x_k^2 - 2 x_k y_j + d y_j^2]/(2b)) f_k,
- * with y_j = 4 b x_j / pi (Algorithm).  For b = 0 the definition of §1 reads
+ * O1: discrete LCT as the Riemann sum of the definition of §1, for samples
+ * f_k = f(xi_k) taken on the input grid xi_k = s x_k (s > 0; s = 1 is the
+ * Algorithm's grid), quadrature weight s h:
+ *   G_j = sum_k s h (2 pi i b)^(-1/2) exp(i [a xi_k^2 - 2 xi_k y_j + d y_j^2]/(2b)) f_k,
+ * at the output nodes y_j = 4 b x_j / (pi s) (the Algorithm's y_j for s = 1;
+ * for other s the nodes that keep the cross term a DFT).  For b = 0 the
+ * definition of §1 reads
  *   G(y) = sqrt(d) exp(i c d y^2 / 2) f(d y)
- * and with y_j = x_j / d this is sqrt(d) exp(i c x_j^2 / (2d)) f_j.
+ * and with y_j = xi_j / d this is sqrt(d) exp(i c xi_j^2 / (2d)) f_j.
  *
  * The three phase terms are written in the variables n_j, n_k, which is an
- * exact substitution of x and y:
- *   a x_k^2/(2b)   = a pi^2 n_k^2 / (16 b N)
- *   x_k y_j / b    = pi n_j n_k / (2N)        (reduced exactly modulo 4N)
- *   d y_j^2/(2b)   = b d n_j^2 / N
+ * exact substitution of xi and y:
+ *   a xi_k^2/(2b)  = a s^2 pi^2 n_k^2 / (16 b N)
+ *   xi_k y_j / b   = pi n_j n_k / (2N)        (reduced exactly modulo 4N)
+ *   d y_j^2/(2b)   = b d n_j^2 / (N s^2)
  * so no phase of magnitude 1e4..1e7 rad is rounded before its reduction.
  *
  * rows == NULL means every row 0..N-1 (then nrows must be N).
  * Returns 0, or -1 on bad arguments.
  * Pinned: closed form eq. (exa1), Hermite-Gauss closed form, unitarity,
- * numpy FFT for a=d=0, b=1, composition law, mpmath brute force.
+ * numpy FFT for a=d=0, b=1, composition law, mpmath brute force; for s != 1
+ * the Gaussian closed form on scaled grids and a chain of two transforms
+ * against the closed form of the matrix product.
  */
-int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
-                    const double *f, const int64_t *rows, int64_t nrows,
-                    double *out)
+int oracle_lct_rows_scaled(int64_t N, double a, double b, double c, double d, double s,
+                           const double *f, const int64_t *rows, int64_t nrows,
+                           double *out)
 {
-    if (N < 1 || f == NULL || out == NULL || nrows < 0)
+    if (N < 1 || f == NULL || out == NULL || nrows < 0 || !(s > 0.0) || !isfinite(s))
         return -1;
     if (rows == NULL && nrows != N)
         return -1;
     const long double h = PI_L / sqrtl(2.0L * (long double)N);
+    const long double S = (long double)s;
 
     if (b == 0.0) {
         if (d == 0.0)
@@ -99,7 +106,7 @@ int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
             if (j < 0 || j >= N)
                 return -1;
             long double xj = node_l(N, j);
-            long double ph = (long double)c * xj * xj / (2.0L * (long double)d);
+            long double ph = (long double)c * S * S * xj * xj / (2.0L * (long double)d);
             long double complex v = sd * cexpl(CMPLXL(0.0L, ph)) *
                                     CMPLXL((long double)f[2 * j], (long double)f[2 * j + 1]);
             out[2 * r] = (double)creall(v);
@@ -109,14 +116,14 @@ int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
     }
 
     const long double A = (long double)a, B = (long double)b, D = (long double)d;
-    const long double complex amp = h * inv_sqrt_2pi_i_b(B);
+    const long double complex amp = S * h * inv_sqrt_2pi_i_b(B);
     /* per-k pre phase a x_k^2/(2b) (hoisted out of the row loop) */
     long double *t1 = (long double *)malloc(sizeof(long double) * (size_t)N);
     if (!t1)
         return -1;
     for (int64_t k = 0; k < N; ++k) {
         long double nk = (long double)(2 * k - N + 1);
-        t1[k] = A * PI_L * PI_L * nk * nk / (16.0L * B * (long double)N);
+        t1[k] = A * S * S * PI_L * PI_L * nk * nk / (16.0L * B * (long double)N);
     }
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -127,7 +134,7 @@ int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
             continue;
         }
         int64_t nj = 2 * j - N + 1;
-        long double t3 = B * D * (long double)nj * (long double)nj / (long double)N;
+        long double t3 = B * D * (long double)nj * (long double)nj / ((long double)N * S * S);
         long double sr = 0.0L, si = 0.0L;
         for (int64_t k = 0; k < N; ++k) {
             int64_t nk = 2 * k - N + 1;
@@ -149,6 +156,14 @@ int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
     }
     free(t1);
     return bad ? -1 : 0;
+}
+
+/* The Algorithm's grid (s = 1). */
+int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
+                    const double *f, const int64_t *rows, int64_t nrows,
+                    double *out)
+{
+    return oracle_lct_rows_scaled(N, a, b, c, d, 1.0, f, rows, nrows, out);
 }
 
 /*

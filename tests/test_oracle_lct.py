@@ -182,6 +182,81 @@ def test_composition_law():
     assert e < 1e-12
 
 
+SCALED_CASES = [(0.45, (0.7, 1.3, 0.4)), (0.45, (1.9, 0.25, -0.8)), (2.2, (0.7, 1.3, 0.4)),
+                (2.2, (-1.2, -0.6, 1.5)), (1.37, (-0.3, 0.8, 2.1))]
+
+
+@pytest.mark.parametrize("s,M", SCALED_CASES)
+def test_scaled_grid_gaussian_closed_form(s, M):
+    """Input grid s x_k (the scaling step of the scaling-chirp-DFT-chirp-scaling form, §1 and §3):
+    samples of a complex Gaussian on s x_k, outputs at y_j = 4 b x_j / (pi s), checked against
+    the textbook Gaussian integral of the LCT.  A dropped s in the pre-chirp, post-chirp,
+    quadrature weight or output nodes gives O(1) errors here."""
+    a, b, d = M
+    c = (a * d - 1) / b
+    N = 1024
+    xi = s * oracle.nodes(N)
+    al, be, ga = 0.5 + 0.3j, 0.4 - 0.2j, 0.1
+    G = oracle.lct(np.exp(-(al * xi * xi + 2 * be * xi + ga)), a, b, c, d, scale=s)
+    y = oracle.output_nodes(N, b, d, scale=s)
+    assert np.allclose(y, 4 * b * oracle.nodes(N) / (np.pi * s), rtol=1e-15, atol=0)
+    assert relerr(G, gaussian_lct(y, al, be, ga, a, b, d)) < 1e-13
+
+
+@pytest.mark.parametrize("s", [0.6, 1.8])
+def test_scaled_grid_b_zero(s):
+    """b = 0 on the grid s x_k: G(y_j) = sqrt(d) e^(i c d y_j^2/2) f(d y_j) at y_j = s x_j / d."""
+    N = 300
+    xi = s * oracle.nodes(N)
+    fx = lambda t: np.exp(-(0.6 * t * t + 0.4 * t + 0.1)).astype(np.complex128)
+    for (a, c) in [(2.0, 0.7), (-0.5, 1.2)]:
+        d = 1.0 / a
+        y = oracle.output_nodes(N, 0.0, d, scale=s)
+        G = oracle.lct(fx(xi), a, 0.0, c, d, scale=s)
+        ref = np.sqrt(complex(d)) * np.exp(1j * c * d * y * y / 2) * fx(d * y)
+        assert relerr(G, ref) < 1e-14
+
+
+@pytest.mark.parametrize("M1,M2", [((0.7, 1.3, 0.4), (0.6, 0.9, 1.1)), ((-1.2, -0.6, 1.5), (1.1, 0.5, 0.2)),
+                                   ((0.3, 2.0, 0.9), (0.8, -0.7, -0.4))])
+def test_scaled_chain_matches_product_closed_form(M1, M2):
+    """Two transforms in a row without resampling: the first one's outputs lie on
+    (4 b2 / pi) x_j, i.e. on the grid sigma x_k with sigma = 4 |b2| / pi (reversed when b2 < 0,
+    since x_{N-1-j} = -x_j); the second one takes them at scale sigma.  The result is the LCT of
+    the product M1 M2 (the composition law) at y_j = 4 b1 x_j / (pi sigma), checked against the
+    closed form of that product."""
+    N = 1024
+    x = oracle.nodes(N)
+    al, be, ga = 0.5 + 0.3j, 0.4 - 0.2j, 0.1
+    f = np.exp(-(al * x * x + 2 * be * x + ga))
+    (a1, b1, d1), (a2, b2, d2) = M1, M2
+    c1, c2 = (a1 * d1 - 1) / b1, (a2 * d2 - 1) / b2
+    sig = 4 * abs(b2) / np.pi
+    G1 = oracle.lct(f, a2, b2, c2, d2)
+    if b2 < 0:
+        G1 = G1[::-1]
+    G = oracle.lct(G1, a1, b1, c1, d1, scale=sig)
+    P = np.array([[a1, b1], [c1, d1]]) @ np.array([[a2, b2], [c2, d2]])
+    y = oracle.output_nodes(N, b1, d1, scale=sig)
+    ref = gaussian_lct(y, al, be, ga, P[0, 0], P[0, 1], P[1, 1])
+    assert relerr(G, ref) < 1e-13
+
+
+def test_scale_one_is_the_algorithm_grid():
+    """scale = 1 reproduces the unscaled transform bit for bit."""
+    g = np.random.default_rng(5)
+    f = g.standard_normal(96) + 1j * g.standard_normal(96)
+    M = (1.7, -0.4, 0.3, (1 - 0.4 * 0.3) / 1.7)
+    assert np.array_equal(oracle.lct(f, *M), oracle.lct(f, *M, scale=1.0))
+
+
+def test_scale_rejects_nonpositive():
+    f = np.ones(8, dtype=np.complex128)
+    for s in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(ValueError):
+            oracle.lct(f, 0.5, 1.0, -0.5, 1.0, scale=s)
+
+
 @pytest.mark.parametrize("N,M", [(8, (0.5, 1.0, -0.5, 1.0)), (15, (1.9, -0.3, 2.0, (1 - 0.6) / 1.9)),
                                  (32, (-1.2, 1.7, 0.4, (1 + 1.7 * 0.4) / -1.2))])
 def test_mpmath_brute_force(N, M):
