@@ -81,6 +81,26 @@ typedef struct lct_plan_s *lct_plan;
 int lct_plan_create(lct_plan *out, int64_t N, double a, double b, double c, double d);
 int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, double d,
                        lct_precision prec);
+/*
+ * Plan for samples taken on the scaled input grid xi_k = s x_k, s > 0 finite
+ * (the first "scaling" of the scaling-chirp-DFT-chirp-scaling form, §1 and
+ * §3): out[j] approximates G(y_j) at y_j = 4 b x_j / (pi s) for b != 0, and
+ * y_j = s x_j / d for b == 0 (lct_nodes_scaled).  It is the Riemann sum of
+ * the integral of §1 with weight s h:
+ *   out[j] = s h (2 pi i b)^(-1/2) sum_k exp(i [a xi_k^2 - 2 xi_k y_j + d y_j^2]/(2b)) in[k],
+ * the same DFT with the pre-chirp a s^2 x_k^2/(2b), the post-chirp
+ * d y_j^2/(2b) at the scaled y_j, and the amplitude times s, all derived
+ * here in extended precision (one set of constants per plan).  This lets one
+ * transform read another's output without resampling: after a transform with
+ * parameter b1 > 0 the samples lie on s = 4 b1 / pi (for b1 < 0, reverse them
+ * first: they lie on s = 4 |b1| / pi in descending order).  s == 1 is
+ * lct_plan_create_ex.  lct_exec and lct_exec_adjoint take the scale into
+ * account; frft_exec / frft_exec_ws return LCT_ERR_UNSUPPORTED for s != 1.
+ * Errors: those of lct_plan_create_ex; LCT_ERR_ARG if s is not a finite
+ * positive number or the scaled constants overflow.  *out is NULL on error.
+ */
+int lct_plan_create_scaled(lct_plan *out, int64_t N, double a, double b, double c, double d, double s,
+                           lct_precision prec);
 void lct_plan_destroy(lct_plan p);
 
 /*
@@ -246,6 +266,14 @@ void lct_tune_clear(void);
  * Host memory.  Returns LCT_ERR_ARG for N < 1 or b == d == 0.
  */
 int lct_nodes(int64_t N, double b, double d, double *x, double *y);
+
+/*
+ * Host helper for plans on the scaled grid (lct_plan_create_scaled): input
+ * nodes x (N doubles, s x_k) and output nodes y (N doubles: 4 b x_k / (pi s),
+ * or s x_k / d when b == 0).  Either pointer may be NULL.  Host memory.
+ * Returns LCT_ERR_ARG for N < 1, b == d == 0, or s not finite and positive.
+ */
+int lct_nodes_scaled(int64_t N, double b, double d, double s, double *x, double *y);
 
 /* Static description of a return code. */
 const char *lct_strerror(int code);

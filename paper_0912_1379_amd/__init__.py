@@ -20,6 +20,8 @@ The functions named like the C entry points take and return torch tensors:
     y = frft_exec(plan, z, x)             # same-grid fractional transform
     y = frft_exec_many(x, Z2)             # Z2: (batch, 2) float64 (re z, im z)
     x, y = lct_nodes(N, b, d)             # input / output nodes (numpy)
+    plan = lct_plan_create(N, a, b, c, d, scale=s)   # samples on s x_k
+    x, y = lct_nodes(N, b, d, scale=s)
 
 ``lct(x, M)`` and ``frft(x, z)`` are conveniences; ``LCTFunction`` is the
 autograd function whose backward is the adjoint transform plus the
@@ -38,7 +40,7 @@ from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODU
                    LCT_FP32_SPLITBF16, LCT_OK, LCT_TUNE_FRFT, LCT_TUNE_LCT, LctError)
 
 __all__ = [
-    "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_destroy", "lct_exec", "lct_exec_many",
+    "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_create_scaled", "lct_plan_destroy", "lct_exec", "lct_exec_many",
     "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
     "frft_workspace_size", "RaggedPlan", "make_descriptors", "lct_ragged_plan_create", "lct_exec_ragged",
     "LCT_KIND_LCT", "LCT_KIND_FRFT",
@@ -96,15 +98,17 @@ def _out_like(x: torch.Tensor, out):
 class Plan:
     """Owns an ``lct_plan`` handle (one size, one matrix, one precision)."""
 
-    def __init__(self, N: int, a: float, b: float, c: float, d: float, precision: int = LCT_FP32):
+    def __init__(self, N: int, a: float, b: float, c: float, d: float, precision: int = LCT_FP32,
+                 scale: float = 1.0):
         lib = _lib.load()
         h = ctypes.c_void_p()
-        _lib.check(lib.lct_plan_create_ex(ctypes.byref(h), int(N), float(a), float(b), float(c), float(d),
-                                          int(precision)), "lct_plan_create_ex")
+        _lib.check(lib.lct_plan_create_scaled(ctypes.byref(h), int(N), float(a), float(b), float(c), float(d),
+                                              float(scale), int(precision)), "lct_plan_create_scaled")
         self._h = h
         self.N = int(N)
         self.M = (float(a), float(b), float(c), float(d))
         self.precision = int(precision)
+        self.scale = float(scale)
 
     @property
     def handle(self):
@@ -122,11 +126,16 @@ class Plan:
             pass
 
 
-def lct_plan_create(N, a, b, c, d, precision: int = LCT_FP32) -> Plan:
-    return Plan(N, a, b, c, d, precision)
+def lct_plan_create(N, a, b, c, d, precision: int = LCT_FP32, scale: float = 1.0) -> Plan:
+    """Plan for samples on the input grid scale * x_k (scale 1: the Algorithm's x_k)."""
+    return Plan(N, a, b, c, d, precision, scale)
 
 
 lct_plan_create_ex = lct_plan_create
+
+
+def lct_plan_create_scaled(N, a, b, c, d, s: float, precision: int = LCT_FP32) -> Plan:
+    return Plan(N, a, b, c, d, precision, s)
 
 
 def lct_plan_destroy(plan: Plan) -> None:
@@ -397,13 +406,18 @@ def lct_tune_clear() -> None:
     _lib.load().lct_tune_clear()
 
 
-def lct_nodes(N: int, b: float, d: float = 1.0):
-    """Input nodes x_k (eq. asymcer) and output nodes y_j (numpy float64)."""
+def lct_nodes(N: int, b: float, d: float = 1.0, scale: float = 1.0):
+    """Input nodes (scale * x_k, eq. asymcer) and output nodes y_j (numpy float64)."""
     x = np.empty(N, dtype=np.float64)
     y = np.empty(N, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
-    rc = _lib.load().lct_nodes(int(N), float(b), float(d), x.ctypes.data_as(dp), y.ctypes.data_as(dp))
-    _lib.check(rc, "lct_nodes")
+    if scale == 1.0:
+        rc = _lib.load().lct_nodes(int(N), float(b), float(d), x.ctypes.data_as(dp), y.ctypes.data_as(dp))
+        _lib.check(rc, "lct_nodes")
+    else:
+        rc = _lib.load().lct_nodes_scaled(int(N), float(b), float(d), float(scale), x.ctypes.data_as(dp),
+                                          y.ctypes.data_as(dp))
+        _lib.check(rc, "lct_nodes_scaled")
     return x, y
 
 

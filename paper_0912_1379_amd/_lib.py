@@ -47,6 +47,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "lct_plan_create": (_int, [ctypes.POINTER(_vp), _i64, _d, _d, _d, _d]),
     "lct_plan_create_ex": (_int, [ctypes.POINTER(_vp), _i64, _d, _d, _d, _d, _int]),
+    "lct_plan_create_scaled": (_int, [ctypes.POINTER(_vp), _i64, _d, _d, _d, _d, _d, _int]),
     "lct_plan_destroy": (None, [_vp]),
     "lct_exec": (_int, [_vp, _vp, _vp, _i64, _vp]),
     "lct_exec_many": (_int, [_i64, _int, _vp, _vp, _vp, _i64, _vp]),
@@ -71,6 +72,7 @@ SIGNATURES = {
     "lct_tune_save": (_int, [ctypes.c_char_p]),
     "lct_tune_clear": (None, []),
     "lct_nodes": (_int, [_i64, _d, _d, _dp, _dp]),
+    "lct_nodes_scaled": (_int, [_i64, _d, _d, _d, _dp, _dp]),
     "lct_strerror": (ctypes.c_char_p, [_int]),
     "lct_max_single_pass": (_i64, [_int]),
 }

@@ -15,6 +15,7 @@ struct lct_plan_s {
     int64_t N;
     int prec;
     double a, b, c, d;
+    double s; // input grid scale: samples on s x_k
     LctConst k;
 };
 
@@ -49,6 +50,47 @@ int validate_M(double a, double b, double c, double d)
     if (fabs(ad - bc - 1.0) > tol)
         return LCT_ERR_NOT_UNIMODULAR;
     return LCT_OK;
+}
+
+// Constants of the transform of samples taken on the input grid xi_k = s x_k
+// (s > 0), outputs at y_j = 4 b x_j / (pi s) for b != 0 and xi_j / d for b = 0.
+// The Riemann sum of the integral of §1 on that grid keeps the cross phase
+// xi_k y_j / b = pi n_j n_k / (2N) (still a DFT) and changes
+//   pre  a xi_k^2 / (2b) = a s^2 pi^2 n_k^2 / (16 b N) rad
+//   post d y_j^2 / (2b)  = b d n_j^2 / (N s^2) rad
+//   amplitude            s h (2 pi i b)^(-1/2)  (the quadrature weight is s h)
+// and for b = 0 the chirp c xi_j^2 / (2d) = c s^2 pi^2 n_j^2 / (16 N d) rad with
+// the amplitude sqrt(d) unchanged.  Coefficients in double-double as in
+// lct_const, so s costs no precision; s == 1 is lct_const itself.
+LctConst lct_const_scaled(int64_t N, double a, double b, double c, double d, double s)
+{
+    LctConst k = lct_const(N, a, b, c, d);
+    if (s == 1.0)
+        return k;
+    const DD pi{PI_HI, PI_LO};
+    if (b == 0.0) {
+        const DD t = dd_div_d(dd_div_d(dd_mul_d(dd_mul_d(dd_mul_d(pi, c), s), s), d), 32.0 * (double)N);
+        k.post_hi = t.hi;
+        k.post_lo = t.lo;
+        return k;
+    }
+    const DD pre = dd_div_d(dd_div_d(dd_mul_d(dd_mul_d(dd_mul_d(pi, a), s), s), b), 32.0 * (double)N);
+    const DD post =
+        dd_div_d(dd_div_d(dd_div_d(dd_mul(dd_two_prod(b, d), DD{INV2PI_HI, INV2PI_LO}), (double)N), s), s);
+    k.pre_hi = pre.hi;
+    k.pre_lo = pre.lo;
+    k.post_hi = post.hi;
+    k.post_lo = post.lo;
+    k.amp_re *= s;
+    k.amp_im *= s;
+    k.amp_mag *= s;
+    return k;
+}
+
+bool lct_const_finite(const LctConst &k)
+{
+    return isfinite(k.pre_hi) && isfinite(k.pre_lo) && isfinite(k.post_hi) && isfinite(k.post_lo) &&
+           isfinite(k.amp_mag) && k.amp_mag > 0.0;
 }
 
 int lct_run(int64_t N, bool fp64, bool mf, const double *M4, const LctConst *k, int mode, const void *in, void *out,
@@ -243,7 +285,31 @@ int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, d
     p->b = b;
     p->c = c;
     p->d = d;
+    p->s = 1.0;
     p->k = lct_const(N, a, b, c, d);
+    *out = p;
+    return LCT_OK;
+}
+
+int lct_plan_create_scaled(lct_plan *out, int64_t N, double a, double b, double c, double d, double s,
+                           lct_precision prec)
+{
+    if (out == nullptr)
+        return LCT_ERR_ARG;
+    *out = nullptr;
+    if (!isfinite(s) || !(s > 0.0))
+        return LCT_ERR_ARG;
+    lct_plan p = nullptr;
+    int rc = lct_plan_create_ex(&p, N, a, b, c, d, prec);
+    if (rc)
+        return rc;
+    const LctConst k = lct_const_scaled(N, a, b, c, d, s);
+    if (!lct_const_finite(k)) {
+        delete p;
+        return LCT_ERR_ARG;
+    }
+    p->s = s;
+    p->k = k;
     *out = p;
     return LCT_OK;
 }
@@ -336,6 +402,8 @@ int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, i
         return LCT_ERR_ARG;
     if (p->prec == LCT_FP32_SPLITBF16)
         return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
+    if (p->s != 1.0)
+        return LCT_ERR_UNSUPPORTED; // the same-grid fractional transform is defined on x_k only
     if (!isfinite(z_re) || !isfinite(z_im))
         return LCT_ERR_ARG;
     if (hypot(z_re, z_im) > 1.0 + 1e-12)
@@ -351,6 +419,8 @@ int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out
         return LCT_ERR_ARG;
     if (p->prec == LCT_FP32_SPLITBF16)
         return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
+    if (p->s != 1.0)
+        return LCT_ERR_UNSUPPORTED; // the same-grid fractional transform is defined on x_k only
     if (!isfinite(z_re) || !isfinite(z_im))
         return LCT_ERR_ARG;
     if (hypot(z_re, z_im) > 1.0 + 1e-12)
@@ -402,6 +472,22 @@ int lct_nodes(int64_t N, double b, double d, double *x, double *y)
             x[k] = (double)xk;
         if (y)
             y[k] = (double)(b != 0.0 ? 4.0L * (long double)b * xk / pi : xk / (long double)d);
+    }
+    return LCT_OK;
+}
+
+int lct_nodes_scaled(int64_t N, double b, double d, double s, double *x, double *y)
+{
+    if (N < 1 || (b == 0.0 && d == 0.0) || !isfinite(s) || !(s > 0.0))
+        return LCT_ERR_ARG;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double h = pi / sqrtl(2.0L * (long double)N), S = s;
+    for (int64_t k = 0; k < N; ++k) {
+        long double xk = h * (long double)(2 * k - N + 1) / 2.0L;
+        if (x)
+            x[k] = (double)(S * xk);
+        if (y)
+            y[k] = (double)(b != 0.0 ? 4.0L * (long double)b * xk / (pi * S) : S * xk / (long double)d);
     }
     return LCT_OK;
 }

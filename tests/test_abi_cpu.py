@@ -94,6 +94,43 @@ def test_nodes_helper_matches_oracle(lib, N, b, d):
     assert lib.lct_nodes(0, 1.0, 1.0, None, None) == _lib.LCT_ERR_ARG
 
 
+def test_scaled_plan_validation(lib):
+    def sp(s, M=(1.0, 2.0, 0.5, 2.0), N=64, prec=0):
+        h = ctypes.c_void_p()
+        rc = lib.lct_plan_create_scaled(ctypes.byref(h), N, *M, s, prec)
+        if rc == 0:
+            assert h.value
+            lib.lct_plan_destroy(h)
+        else:
+            assert not h.value
+        return rc
+    assert sp(1.0) == sp(2.5) == sp(1e-3) == sp(0.7, M=(2.0, 0.0, 0.7, 0.5)) == _lib.LCT_OK
+    for s in (0.0, -1.0, float("nan"), float("inf"), 1e-300, 1e300):
+        assert sp(s) == _lib.LCT_ERR_ARG, s
+    assert sp(2.0, M=(1.0, 2.0, 0.5, 2.1)) == _lib.LCT_ERR_NOT_UNIMODULAR
+    assert sp(2.0, N=7) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert lib.lct_plan_create_scaled(None, 64, 1.0, 2.0, 0.5, 2.0, 2.0, 0) == _lib.LCT_ERR_ARG
+    h = ctypes.c_void_p()
+    assert lib.lct_plan_create_scaled(ctypes.byref(h), 64, 1.0, 2.0, 0.5, 2.0, 2.0, 0) == 0
+    # the same-grid fractional transform is defined on x_k only
+    assert lib.frft_exec(h, 0.5, 0.2, 8, 16, 1, None) == _lib.LCT_ERR_UNSUPPORTED
+    assert lib.frft_exec_ws(h, 0.5, 0.2, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_UNSUPPORTED
+    lib.lct_plan_destroy(h)
+
+
+@pytest.mark.parametrize("N,b,d,s", [(1, 1.0, 1.0, 2.0), (7, -0.3, 2.0, 0.4), (4096, 2.0, 0.5, 1.7),
+                                     (100, 0.0, -2.0, 3.1), (64, 0.9, 1.0, 1.0)])
+def test_scaled_nodes_helper_matches_oracle(lib, N, b, d, s):
+    x = np.empty(N)
+    y = np.empty(N)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.lct_nodes_scaled(N, b, d, s, x.ctypes.data_as(dp), y.ctypes.data_as(dp)) == 0
+    assert np.allclose(x, s * oracle.nodes(N), rtol=1e-15, atol=1e-13)
+    assert np.allclose(y, oracle.output_nodes(N, b, d, scale=s), rtol=1e-15, atol=1e-13)
+    assert lib.lct_nodes_scaled(N, b, d, 0.0, None, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_nodes_scaled(N, b, d, float("nan"), None, None) == _lib.LCT_ERR_ARG
+
+
 # --- autotuner table (host functions only) ------------------------------------
 def _cands(lib, N, prec, kind):
     n = ctypes.c_int(0)
