@@ -162,13 +162,20 @@ int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *
                    int64_t batch, hipStream_t stream);
 
 /*
- * When 2N exceeds the single-pass limit the convolution runs as two-pass FFTs
- * through a caller-owned DEVICE workspace (16-byte aligned) of
- * frft_workspace_size(N, prec, batch) bytes (0 when none is needed):
- * 2 x 2N complex samples per signal (the data's and the kernel's spectra; the
- * first also holds the inverse transform's intermediate).  Without enough
- * workspace the calls return LCT_ERR_WORKSPACE and do nothing.  in != out is
- * required.
+ * Workspace: a caller-owned DEVICE buffer (16-byte aligned) of
+ * frft_workspace_size(N, prec, batch) bytes.
+ *  - 2N above the single-pass limit: the convolution runs as two-pass FFTs
+ *    through 2 x 2N complex samples per signal (the data's and the kernel's
+ *    spectra; the first also holds the inverse transform's intermediate).
+ *    Required: without enough workspace the calls return LCT_ERR_WORKSPACE
+ *    and do nothing.
+ *  - Single pass: 2N complex samples, optional.  frft_exec_ws with such a
+ *    workspace computes the DFT of the Gaussian-chirp kernel once for the
+ *    whole batch (its order is shared) and every signal reuses it: two
+ *    length-2N FFTs per signal instead of three.  Without it (or in
+ *    frft_exec / frft_exec_many[_ws], whose orders may differ per signal)
+ *    each signal transforms the kernel itself.  The results agree to rounding.
+ * in != out is required.
  */
 size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch);
 int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,

@@ -262,7 +262,8 @@ def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None, ws=
     batch = _batch_of(x, N)
     _check_params(Z2, batch, 2, "Z2")
     out = _out_like(x, out)
-    need = frft_workspace_size(N, prec, batch)
+    # one order per signal: only the two-pass sizes use a workspace
+    need = frft_workspace_size(N, prec, batch) if 2 * N > lct_max_single_pass(prec) else 0
     if ws is None:
         ws = _workspace(need, x.device)
     rc = _lib.load().frft_exec_many_ws(N, prec, Z2.data_ptr(), x.data_ptr(), out.data_ptr(), batch,
@@ -477,7 +478,17 @@ def frft(x: torch.Tensor, z) -> torch.Tensor:
     if isinstance(z, torch.Tensor):
         zc = z.to(torch.complex128).reshape(batch)
         Z2 = torch.view_as_real(zc).to(device=x.device).contiguous()
-    else:
-        z = complex(z)
-        Z2 = torch.tensor([[z.real, z.imag]], dtype=torch.float64, device=x.device).expand(batch, 2).contiguous()
-    return frft_exec_many(x, Z2)
+        return frft_exec_many(x, Z2)
+    # one order for every signal: the plan path shares the kernel's spectrum
+    return frft_exec(_frft_plan(N, _prec_of(x)), complex(z), x)
+
+
+_FRFT_PLANS: dict = {}
+
+
+def _frft_plan(N: int, precision: int) -> Plan:
+    """A plan of size N (the fractional transform uses only its size and precision)."""
+    key = (int(N), int(precision))
+    if key not in _FRFT_PLANS:
+        _FRFT_PLANS[key] = Plan(N, 1.0, 0.0, 0.0, 1.0, precision)
+    return _FRFT_PLANS[key]

@@ -360,16 +360,35 @@ __global__ __launch_bounds__(LB) void k_frft(
         }
     }
 
-    // 1) kernel t_m at circular position p: m = min(p, L - p)
+    // 1) kernel t_m at circular position p: m = min(p, L - p), and its DFT;
+    // with one order for the whole batch the DFT is computed once (SPEC_WRITE)
+    // and loaded by every signal (SPEC_READ), in natural order p = t + T e
     C<R> K[E];
+    if (args.spec_mode == SPEC_READ) {
+        const V *sp = reinterpret_cast<const V *>(args.spec);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int p = t + T * e;
-        const int m = p <= N ? p : L - p;
-        const double m2 = (double)m * (double)m;
-        K[e] = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, m2);
+        for (int e = 0; e < E; ++e)
+            K[e] = ldc<R>(sp + t + T * e);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = t + T * e;
+            const int m = p <= N ? p : L - p;
+            const double m2 = (double)m * (double)m;
+            K[e] = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, m2);
+        }
+        fft_any<R, E, LFIX>(K, lds, t, T, sc);
+        if (args.spec_mode == SPEC_WRITE) {
+            // launched as one work-group; slot 0 holds the spectrum
+            if (sl == 0) {
+                V *sp = reinterpret_cast<V *>(args.spec);
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    stc<R>(sp + t + T * e, K[e]);
+            }
+            return;
+        }
     }
-    fft_any<R, E, LFIX>(K, lds, t, T, sc);
 
     // 2) data e^{-P x_k^2} f_k (reversed for Hankel), zero-padded to L
     C<R> v[E];

@@ -113,10 +113,13 @@ int lct_run(int64_t N, bool fp64, bool mf, const double *M4, const LctConst *k, 
     return lct_launch(tl, N, fp64, M4, k, mode, in, out, batch, s);
 }
 
+// Single pass: room for the kernel spectrum of a shared order (2N complex
+// values; optional, used by frft_exec_ws).  Two passes: data and kernel
+// regions of 2N complex values per signal (required).
 size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
 {
     if (2 * N <= single_pass_limit(fp64))
-        return 0;
+        return (size_t)(2 * N) * (fp64 ? 16 : 8);
     return (size_t)batch * 2 * (size_t)(2 * N) * (fp64 ? 16 : 8);
 }
 
@@ -146,7 +149,12 @@ int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const voi
     const Tiling tl = select_tiling(LCT_TUNE_FRFT, N, 2 * N, fp64, 0);
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;
-    return frft_sp_launch(tl, N, fp64, Z2, k, in, out, batch, s);
+    // one order for the whole batch and room for its spectrum: transform the
+    // kernel once instead of once per signal
+    void *spec = nullptr;
+    if (Z2 == nullptr && ws != nullptr && ws_bytes >= frft_ws_bytes(N, fp64, batch) && ((uintptr_t)ws) % 16 == 0)
+        spec = ws;
+    return frft_sp_launch(tl, N, fp64, Z2, k, in, out, batch, s, spec);
 }
 
 } // namespace
@@ -208,7 +216,7 @@ int fs_launch(const FsTiling &f, int64_t N, bool fp64, const double *M4, const L
 }
 
 int frft_sp_launch(const Tiling &tl, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
-                   void *out, int64_t batch, hipStream_t s)
+                   void *out, int64_t batch, hipStream_t s, void *spec)
 {
     FrArgs a{};
     a.N = (int)N;
@@ -222,6 +230,20 @@ int frft_sp_launch(const Tiling &tl, int64_t N, bool fp64, const double *Z2, con
     const int64_t nb = (batch + tl.S - 1) / tl.S;
     if (nb > INT32_MAX)
         return LCT_ERR_ARG;
+    if (spec != nullptr && Z2 == nullptr && k != nullptr && !k->special) {
+        // the kernel's spectrum once: one work-group, one slot
+        FrArgs w = a;
+        w.S = 1;
+        w.batch = 1;
+        w.spec_mode = SPEC_WRITE;
+        w.spec = spec;
+        const size_t lds1 = (size_t)lds_elems((int)(2 * N)) * (fp64 ? 16 : 8);
+        hipError_t e = launch_frft(fp64, tl.E, in, out, w, 1, tl.T, lds1, s);
+        if (e != hipSuccess)
+            return LCT_ERR_HIP;
+        a.spec_mode = SPEC_READ;
+        a.spec = spec;
+    }
     return hip_status(launch_frft(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
 }
 

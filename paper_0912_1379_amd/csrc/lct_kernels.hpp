@@ -22,15 +22,21 @@ struct LctArgs {
     Sched sc;       // radix schedule of the length-N DFT
 };
 
+// Kernel-spectrum modes of the single-pass fractional transform.
+enum { SPEC_NONE = 0, SPEC_WRITE = 1, SPEC_READ = 2 };
+
 struct FrArgs {
     int N;          // signal length (the convolution length is 2N)
     int T;          // threads per signal (2N / E)
     int S;          // signals per work-group
-    int pad_;
+    int spec_mode;  // SPEC_NONE: every signal transforms the kernel itself;
+                    // SPEC_WRITE: one work-group stores the kernel's DFT to `spec`;
+                    // SPEC_READ: every signal loads it from `spec` (one shared order)
     int64_t batch;
     const double *Z2; // per-signal (re z, im z) on the device, or null
     FrConst k;        // constants when Z2 is null
     Sched sc;         // radix schedule of the length-2N DFT
+    void *spec;       // 2N complex values in natural order (SPEC_WRITE / SPEC_READ)
 };
 
 struct FsArgs {

@@ -67,8 +67,11 @@ int lct_launch(const Tiling &tl, int64_t N, bool fp64, const double *M4, const L
                void *out, int64_t batch, hipStream_t s);
 int fs_launch(const FsTiling &f, int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in,
               void *out, int64_t batch, hipStream_t s);
+// spec: when non-null (and k is given, not a z = +-1 order), the kernel's
+// length-2N DFT is computed once into spec (2N complex values) and shared by
+// every signal of the batch.
 int frft_sp_launch(const Tiling &tl, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
-                   void *out, int64_t batch, hipStream_t s);
+                   void *out, int64_t batch, hipStream_t s, void *spec = nullptr);
 int frft_large_launch(const FsTiling &f, int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in,
                       void *out, int64_t batch, void *ws, hipStream_t s);
 int hip_status(hipError_t e);

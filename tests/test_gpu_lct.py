@@ -210,6 +210,34 @@ def test_frft(dtype, tol, N):
         assert rel_rows(y[s], ref)[0] <= tol, (N, z)
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 2e-5), (torch.complex128, 1e-11)])
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 100, 1000, 1536, 4096, 8192])
+def test_frft_shared_order_spectrum(dtype, tol, N):
+    """One order for the batch with a workspace: the kernel's spectrum is computed once and
+    shared (two FFTs per signal).  Against the oracle, and against the per-signal path."""
+    prec = lct.LCT_FP64 if dtype == torch.complex128 else lct.LCT_FP32
+    if 2 * N > lct.lct_max_single_pass(prec):
+        pytest.skip("two-pass size")
+    B = 5
+    gen = np.random.default_rng(300 + N)
+    x = dev(workloads.chirped_gaussians(oracle.nodes(N), workloads.gaussian_params(B, gen)), dtype)
+    fin = x.cpu().numpy().astype(np.complex128)
+    p = lct.lct_plan_create(N, 1.0, 1.0, 0.0, 1.0, precision=prec)
+    need = lct.frft_workspace_size(N, prec, B)
+    assert need == 2 * N * (16 if prec == lct.LCT_FP64 else 8)
+    ws = torch.full((need,), 255, dtype=torch.uint8, device="cuda")
+    rows = None if N <= 4096 else np.random.default_rng(N).choice(N, 128, replace=False)
+    for z in [0.8 * np.exp(-0.6j), -0.55 + 0.3j, 0.999j, 1.0, -1.0]:
+        y = lct.frft_exec(p, z, x, ws=ws).cpu().numpy().astype(np.complex128)
+        Z2 = dev(np.tile([[np.real(z), np.imag(z)]], (B, 1)), torch.float64)
+        y3 = lct.frft_exec_many(x, Z2).cpu().numpy().astype(np.complex128)
+        for s in range(B):
+            ref = oracle.frft(fin[s], z, rows=rows)
+            got = y[s] if rows is None else y[s][rows]
+            assert rel_rows(got, ref)[0] <= tol, (N, z, s)
+            assert rel_rows(y[s], y3[s])[0] <= tol / 4, (N, z, s)
+
+
 def test_frft_plan_and_large():
     N = 8192
     x_n = oracle.nodes(N)
