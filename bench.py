@@ -91,7 +91,10 @@ def make_inputs(B: int, N: int, seed_index: int = 1):
 def time_launches(fn, steps: int, warmup: int):
     """Times `steps` calls on the current stream (the stream the library
     launches on).  Returns (ms per step over the whole timed region, mean ms
-    of the launch itself from an event pair around each call, wall seconds)."""
+    of the launch itself, wall seconds of the timed region).  The timed region
+    holds only the `steps` calls between two events; the per-launch duration
+    comes from a second pass of `steps` calls with an event pair around each,
+    so that those events do not add to the timed region."""
     import torch
 
     for _ in range(warmup):
@@ -99,16 +102,19 @@ def time_launches(fn, steps: int, warmup: int):
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for a, b in ev:
         a.record()
         fn()
         b.record()
-    stop.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     per_launch = sum(a.elapsed_time(b) for a, b in ev) / steps
     return start.elapsed_time(stop) / steps, per_launch, wall
 
@@ -297,6 +303,10 @@ def bench_frft(args):
     }
     # one order for the whole batch (plan path): the kernel's spectrum is
     # computed once per call and shared, two length-2N FFTs per signal
+    if args.no_shared:
+        if not args.no_cpu_baseline:
+            frft_errors(out, x, y, None, z, N)
+        return out
     z0 = complex(z[0])
     plan = lct.lct_plan_create(N, 1.0, 0.0, 0.0, 1.0, precision=lct.LCT_FP32)
     ws = torch.empty(lct.frft_workspace_size(N, lct.LCT_FP32, B), dtype=torch.uint8, device="cuda")
@@ -310,24 +320,31 @@ def bench_frft(args):
     print(f"[bench] frft per-signal order {ms * 1e3:.1f} us, shared order {ms_sh * 1e3:.1f} us",
           file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        import oracle
+        frft_errors(out, x, y, ysh, z, N)
+    return out
 
-        errs = []
-        t0 = time.perf_counter()
-        for s in range(3):
-            fin = x[s].cpu().numpy().astype(np.complex128)
-            ref = oracle.frft(fin, complex(z[s]))
-            errs.append(float(np.linalg.norm(y[s].cpu().numpy() - ref) / np.linalg.norm(ref)))
-        el = time.perf_counter() - t0
-        out["rel_l2"] = {"max": max(errs), "signals": 3}
+
+def frft_errors(out, x, y, ysh, z, N):
+    """Relative L2 errors against the oracle (3 signals of the per-signal-order
+    output, 2 of the shared-order one) and the oracle's own rate."""
+    import oracle
+
+    errs = []
+    t0 = time.perf_counter()
+    for s in range(3):
+        fin = x[s].cpu().numpy().astype(np.complex128)
+        ref = oracle.frft(fin, complex(z[s]))
+        errs.append(float(np.linalg.norm(y[s].cpu().numpy() - ref) / np.linalg.norm(ref)))
+    el = time.perf_counter() - t0
+    out["rel_l2"] = {"max": max(errs), "signals": 3}
+    out["cpu_baseline"] = {"value": 3 * N / el, "unit": "complex samples/s", "cores": oracle.num_threads(),
+                           "kind": "oracle", "sample": f"3 whole signals (dense N={N} sums), {el:.1f} s"}
+    if ysh is not None:
         esh = []
         for s in range(2):
-            ref = oracle.frft(x[s].cpu().numpy().astype(np.complex128), z0)
+            ref = oracle.frft(x[s].cpu().numpy().astype(np.complex128), complex(z[0]))
             esh.append(float(np.linalg.norm(ysh[s].cpu().numpy() - ref) / np.linalg.norm(ref)))
         out["shared_order"]["rel_l2_max"] = max(esh)
-        out["cpu_baseline"] = {"value": 3 * N / el, "unit": "complex samples/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "sample": f"3 whole signals (dense N={N} sums), {el:.1f} s"}
-    return out
 
 
 def bench_fit(args):
@@ -381,6 +398,8 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 matrix-core variant")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-to-device copy reference")
     ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache (flushed) launch timing")
+    ap.add_argument("--no-shared", action="store_true",
+                    help="frft workload: skip the shared-order (precomputed kernel spectrum) leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
     ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft"], default="batched",

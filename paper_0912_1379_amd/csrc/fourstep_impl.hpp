@@ -179,11 +179,8 @@ template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(s
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
     auto kern = a.mode == MODE_FWD ? k_fs1<R, E, MODE_FWD, MF, NFIX, LB> : k_fs1<R, E, MODE_ADJ, MF, NFIX, LB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, (const typename Vec<R>::T *)in, (typename Vec<R>::T *)out,
                        a);
     return hipGetLastError();
@@ -193,11 +190,8 @@ template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(s
 inline hipError_t launch_fs2_t(void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
     auto kern = a.mode == MODE_FWD ? k_fs2<R, E, MODE_FWD, MF, NFIX, LB> : k_fs2<R, E, MODE_ADJ, MF, NFIX, LB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, (typename Vec<R>::T *)out, a);
     return hipGetLastError();
 }

@@ -209,11 +209,8 @@ inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int 
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl1<R, E>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)in, (V *)ws, a);
     return hipGetLastError();
 }
@@ -223,11 +220,8 @@ inline hipError_t launch_frl2_t(void *ws, const FrLArgs &a, int nb, int bs, size
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl2<R, E>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (V *)ws, a);
     return hipGetLastError();
 }
@@ -238,11 +232,8 @@ inline hipError_t launch_frl3_t(const void *ws, void *out, const FrLArgs &a, int
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl3<R, E>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)ws, (V *)out, a);
     return hipGetLastError();
 }

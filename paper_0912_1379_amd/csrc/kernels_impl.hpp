@@ -430,11 +430,8 @@ inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int 
                                hipStream_t s)
 {
     auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD, MF, LB> : k_lct<R, E, NFIX, MODE_ADJ, MF, LB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
                        (typename Vec<R>::T *)out, a);
     return hipGetLastError();
@@ -445,11 +442,8 @@ inline hipError_t launch_pgrad_t(const void *f, const void *g, double *grad4, co
                                  int block, size_t lds, hipStream_t s)
 {
     auto kern = k_lct_pgrad<R, E, NFIX, LB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)f,
                        (const typename Vec<R>::T *)g, grad4, a);
     return hipGetLastError();
@@ -460,11 +454,8 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
                                 hipStream_t s)
 {
     auto kern = k_frft<R, E, LFIX, LB>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
                        (typename Vec<R>::T *)out, a);
     return hipGetLastError();

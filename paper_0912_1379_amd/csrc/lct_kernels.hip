@@ -2,7 +2,31 @@
 // kernels themselves are in kernels_impl.hpp, instantiated in inst_*.hip).
 #include "lct_kernels.hpp"
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 namespace lctk {
+
+hipError_t allow_lds(const void *kern, size_t lds)
+{
+    if (lds <= 65536)
+        return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> granted;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &g = granted[{kern, dev}];
+    if (g >= lds)
+        return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        g = lds;
+    return e;
+}
 
 hipError_t launch_lct(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,
                       hipStream_t s)

@@ -10,6 +10,12 @@
 
 namespace lctk {
 
+// Raises `kern`'s dynamic LDS limit on the current device to at least `lds`
+// bytes when `lds` exceeds the 64 KiB default.  The attribute persists, so it
+// is set once per (kernel, device) and later calls only look it up: setting
+// it on every launch puts a host round trip between back-to-back launches.
+hipError_t allow_lds(const void *kern, size_t lds);
+
 struct LctArgs {
     int N;          // signal length
     int T;          // threads per signal (N / E)
