@@ -33,6 +33,12 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             |u_N| = 1/sqrt(N) identity and Gauss-Hermite weights.
 ``Fz_exact(N, z)``          eq. (tmat); pinned by its eigen-identity and
                             unitarity on |z| = 1.
+``xft(f, z)``               F_z of eq. (tmat) applied to signals sampled at
+                            the zeros of H_N, as sqrt(2 pi) U^T (z^n (U f))
+                            with numpy matmuls; pinned by Fz_exact @ f, the
+                            discrete eigen-identity on the rows of U, and the
+                            O(1/N) approach to the continuum eigen-identity
+                            on sampled Hermite functions.
 """
 from __future__ import annotations
 
@@ -208,6 +214,26 @@ def Fz_exact(N: int, z: complex, U=None) -> np.ndarray:
     F = np.empty((N, N), dtype=np.complex128)
     _load().oracle_Fz_exact(N, _ptr(U), z.real, z.imag, _ptr(F.view(np.float64)))
     return F
+
+
+def xft(f, z: complex, U=None) -> np.ndarray:
+    """Exact-node discrete fractional transform of eq. (tmat) applied to
+    signals f (shape (N,) or (batch, N)) sampled at the zeros of H_N:
+    g = sqrt(2 pi) U^T D(z) U f, D(z) = diag(1, z, ..., z^(N-1)); the powers
+    of z by repeated multiplication in extended precision."""
+    f = np.asarray(f, dtype=np.complex128)
+    one = f.ndim == 1
+    F = f[None, :] if one else f
+    N = F.shape[-1]
+    if U is None:
+        U = hermite_vectors(N)
+    steps = np.full(N, complex(z), dtype=np.clongdouble)
+    steps[0] = 1.0
+    zp = np.cumprod(steps).astype(np.complex128)
+    V = U @ F.T                                   # (N, batch): U f
+    G = np.sqrt(2.0 * np.pi) * (U.T @ (zp[:, None] * V))
+    G = np.ascontiguousarray(G.T)
+    return G[0] if one else G
 
 
 def lct_matrix(N: int, a: float, b: float, c: float, d: float) -> np.ndarray:

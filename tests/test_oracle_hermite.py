@@ -118,3 +118,47 @@ def test_exact_kernel_approaches_asymptotic_kernel():
                 -((1 + z * z) * (x[j] ** 2 + x[k] ** 2) - 4 * x[j] * x[k] * z) / (2 * (1 - z * z))) * dx[k]
             errs.append(abs(F[j, k] - asy) / abs(asy))
     assert max(errs) < 5e-3
+
+
+@pytest.mark.parametrize("N", [1, 5, 64, 200])
+def test_xft_apply_matches_eq_tmat_matrix(N):
+    """The batched apply sqrt(2 pi) U^T D(z) U f equals the matrix of eq. (tmat) times f."""
+    g = np.random.default_rng(N)
+    f = g.standard_normal((3, N)) + 1j * g.standard_normal((3, N))
+    for z in [0.7 * np.exp(0.9j), -0.4 + 0.1j, 1j, 1.0]:
+        F = oracle.Fz_exact(N, z)
+        got = oracle.xft(f, z)
+        ref = (F @ f.T).T
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+        assert np.allclose(oracle.xft(f[1], z), got[1], rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("N", [512, 1024])
+def test_xft_discrete_eigen_identity(N):
+    """Rows of U are eigenvectors: xft(U[n], z) = sqrt(2 pi) z^n U[n]; |z| = 1 keeps the norm."""
+    U = oracle.hermite_vectors(N)
+    rows = [0, 1, 7, N // 2, N - 1]
+    z = np.exp(0.37j)
+    got = oracle.xft(U[rows].astype(np.complex128), z, U)
+    for i, n in enumerate(rows):
+        assert np.abs(got[i] - np.sqrt(2 * np.pi) * z ** n * U[n]).max() < 1e-12
+    f = np.random.default_rng(1).standard_normal(N) + 0j
+    assert abs(np.linalg.norm(oracle.xft(f, z, U)) - np.sqrt(2 * np.pi) * np.linalg.norm(f)) < 1e-11 * np.linalg.norm(f)
+
+
+def test_xft_approaches_continuum_eigen_identity():
+    """The continuum transform maps the Hermite function psi_n to sqrt(2 pi) z^n psi_n
+    (Mehler's formula); the exact-node discretisation reproduces it on sampled psi_n with
+    an error that falls like 1/N (the O(1/N) convergence of the quadrature), and exactly
+    for z = -1 (parity)."""
+    errs = []
+    z = 0.7 * np.exp(0.9j)
+    for N in (64, 256, 1024):
+        x = oracle.hermite_zeros(N)
+        psi = eval_hermite(3, x) * np.exp(-x * x / 2) / np.sqrt(2 ** 3 * math.factorial(3) * np.sqrt(np.pi))
+        ref = np.sqrt(2 * np.pi) * z ** 3 * psi
+        errs.append(np.linalg.norm(oracle.xft(psi, z) - ref) / np.linalg.norm(ref))
+        refm = -np.sqrt(2 * np.pi) * psi
+        assert np.linalg.norm(oracle.xft(psi, -1.0) - refm) < 1e-13 * np.linalg.norm(refm)
+    assert errs[2] < 1e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
