@@ -268,6 +268,38 @@ int lct_tune_save(const char *path);
 void lct_tune_clear(void);
 
 /*
+ * Exact-node discrete fractional transform of §2, eq. (tmat), for a batch of
+ * signals sampled at the N zeros x_0 < ... < x_{N-1} of H_N (not the
+ * asymptotic nodes of eq. asymcer):
+ *   out[s] = F_z in[s],  F_z = sqrt(2 pi) U^T D(z) U,  D(z) = diag(1, z, ..., z^(N-1)),
+ * U the orthogonal matrix of eq. (ortvec), U[n][k] = (u_k)_n.  This is the
+ * O(N^2)-per-signal method the fast transforms approximate; it is evaluated as
+ * two dense products on the matrix cores (FP64 or FP32 arithmetic by the
+ * plan's precision; LCT_FP32_SPLITBF16 gives LCT_ERR_UNSUPPORTED), with the
+ * weights sqrt(2 pi) z^n formed on the device in double-double.
+ *
+ * xft_plan_create computes the zeros (QL eigenvalues of the symmetric
+ * tridiagonal H of §2, polished by Newton steps) and U (recurrence of eq.
+ * receqg, normalised by the Christoffel-Darboux sum) on the host and keeps U
+ * and U^T in plan-owned DEVICE memory (2 N^2 values of the plan's precision);
+ * 1 <= N <= 16384, any N.  xft_exec: in, out DEVICE batch x N complex (in ==
+ * out allowed), |z| <= 1 (beyond 1e-12: LCT_ERR_DOMAIN), ws a caller-owned
+ * DEVICE workspace of xft_workspace_size(N, prec, batch) bytes, 16-byte
+ * aligned (else LCT_ERR_WORKSPACE).  Calls on one plan may run concurrently
+ * only with separate workspaces.
+ * xft_nodes / xft_vectors are host helpers returning the zeros (N doubles) and
+ * U (N x N doubles, row-major) in host memory.
+ */
+typedef struct xft_plan_s *xft_plan;
+int xft_plan_create(xft_plan *out, int64_t N, lct_precision prec);
+void xft_plan_destroy(xft_plan p);
+size_t xft_workspace_size(int64_t N, lct_precision prec, int64_t batch);
+int xft_exec(xft_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch, void *ws,
+             size_t ws_bytes, hipStream_t stream);
+int xft_nodes(int64_t N, double *x);
+int xft_vectors(int64_t N, double *U);
+
+/*
  * Host helper: input nodes x (N doubles, eq. asymcer) and output nodes y
  * (N doubles: 4 b x_j / pi, or x_j / d when b == 0).  Either pointer may be NULL.
  * Host memory.  Returns LCT_ERR_ARG for N < 1 or b == d == 0.

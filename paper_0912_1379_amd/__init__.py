@@ -47,6 +47,7 @@ __all__ = [
     "lct_autotune", "lct_tune_candidates", "lct_tune_get", "lct_tune_set", "lct_tune_load", "lct_tune_save",
     "lct_tune_clear", "LCT_TUNE_LCT", "LCT_TUNE_FRFT",
     "lct_nodes", "lct_strerror", "lct_max_single_pass", "lct", "frft", "LCTFunction", "LctError",
+    "XftPlan", "xft_plan_create", "xft_plan_destroy", "xft_exec", "xft_workspace_size", "xft_nodes", "xft_vectors",
     "LCT_FP32", "LCT_FP64", "LCT_FP32_SPLITBF16",
 ]
 
@@ -420,6 +421,76 @@ def lct_nodes(N: int, b: float, d: float = 1.0, scale: float = 1.0):
                                           y.ctypes.data_as(dp))
         _lib.check(rc, "lct_nodes_scaled")
     return x, y
+
+
+# ---------------------------------------------------------------------------
+# Exact-node discrete fractional transform (eq. tmat)
+# ---------------------------------------------------------------------------
+class XftPlan:
+    """Plan of the exact-node transform F_z = sqrt(2 pi) U^T D(z) U for length N:
+    U and U^T live on the device for the plan's lifetime."""
+
+    def __init__(self, N: int, precision: int = LCT_FP32):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xft_plan_create(ctypes.byref(h), int(N), int(precision)), "xft_plan_create")
+        self._h = h
+        self.N = int(N)
+        self.precision = int(precision)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().xft_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def xft_plan_create(N: int, precision: int = LCT_FP32) -> XftPlan:
+    return XftPlan(N, precision)
+
+
+def xft_plan_destroy(plan: XftPlan) -> None:
+    plan.destroy()
+
+
+def xft_workspace_size(N: int, precision: int, batch: int) -> int:
+    return int(_lib.load().xft_workspace_size(int(N), int(precision), int(batch)))
+
+
+def xft_exec(plan: XftPlan, z: complex, x: torch.Tensor, out=None, stream=None, ws=None) -> torch.Tensor:
+    """F_z applied to every length-N signal of x (sampled at the zeros of H_N,
+    xft_nodes(N)).  A workspace is allocated (torch) when `ws` is not given."""
+    batch, out = _plan_io(plan, x, out)
+    z = complex(z)
+    if ws is None:
+        ws = _workspace(xft_workspace_size(plan.N, plan.precision, batch), x.device)
+    rc = _lib.load().xft_exec(plan.handle, z.real, z.imag, x.data_ptr(), out.data_ptr(), batch,
+                              0 if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
+                              _stream_handle(stream))
+    _lib.check(rc, "xft_exec")
+    return out
+
+
+def xft_nodes(N: int) -> np.ndarray:
+    """The zeros of H_N, ascending (host computation of the library)."""
+    x = np.empty(N, dtype=np.float64)
+    _lib.check(_lib.load().xft_nodes(int(N), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "xft_nodes")
+    return x
+
+
+def xft_vectors(N: int) -> np.ndarray:
+    """U of eq. (ortvec), U[n, k] = (u_k)_n (host computation of the library)."""
+    U = np.empty((N, N), dtype=np.float64)
+    _lib.check(_lib.load().xft_vectors(int(N), U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "xft_vectors")
+    return U
 
 
 def lct_strerror(code: int) -> str:

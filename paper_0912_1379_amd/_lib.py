@@ -72,6 +72,12 @@ SIGNATURES = {
     "lct_tune_save": (_int, [ctypes.c_char_p]),
     "lct_tune_clear": (None, []),
     "lct_nodes": (_int, [_i64, _d, _d, _dp, _dp]),
+    "xft_plan_create": (_int, [ctypes.POINTER(_vp), _i64, _int]),
+    "xft_plan_destroy": (None, [_vp]),
+    "xft_workspace_size": (ctypes.c_size_t, [_i64, _int, _i64]),
+    "xft_exec": (_int, [_vp, _d, _d, _vp, _vp, _i64, _vp, ctypes.c_size_t, _vp]),
+    "xft_nodes": (_int, [_i64, _dp]),
+    "xft_vectors": (_int, [_i64, _dp]),
     "lct_nodes_scaled": (_int, [_i64, _d, _d, _d, _dp, _dp]),
     "lct_strerror": (ctypes.c_char_p, [_int]),
     "lct_max_single_pass": (_i64, [_int]),

@@ -1,0 +1,332 @@
+// xft.hip - the exact-node discrete fractional transform of §2 (eq. tmat):
+// plan (zeros of H_N and the orthonormal vectors of eq. ortvec, computed on
+// the host and kept on the device) and the two matrix-core passes.
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/lct.h"
+#include "lct_kernels.hpp"
+#include "xft_impl.hpp"
+
+using namespace lctk;
+
+struct xft_plan_s {
+    int64_t N;
+    int prec;
+    void *U;  // N x N, U[n][k] = (u_k)_n, in the plan's precision (device)
+    void *Ut; // its transpose (device)
+};
+
+namespace {
+
+constexpr int64_t XFT_MAX_N = 16384;
+
+// Eigenvalues of the symmetric tridiagonal matrix H of §2 (zero diagonal,
+// off-diagonal sqrt(i / 2), i = 1 .. N-1), i.e. the zeros of H_N, by the QL
+// algorithm with implicit Wilkinson shifts (eigenvalues only, O(N^2)).
+// Returns them ascending in d.
+void tridiag_zeros(int64_t N, std::vector<double> &d)
+{
+    d.assign((size_t)N, 0.0);
+    std::vector<double> e((size_t)N, 0.0); // e[i] couples i and i + 1
+    for (int64_t i = 0; i + 1 < N; ++i)
+        e[(size_t)i] = sqrt((double)(i + 1) / 2.0);
+    for (int64_t l = 0; l < N; ++l) {
+        for (int iter = 0; iter < 60; ++iter) {
+            int64_t m = l;
+            for (; m + 1 < N; ++m) {
+                const double dd = fabs(d[(size_t)m]) + fabs(d[(size_t)m + 1]);
+                if (fabs(e[(size_t)m]) <= 2.3e-16 * dd || e[(size_t)m] == 0.0)
+                    break;
+            }
+            if (m == l)
+                break;
+            // Wilkinson shift from the leading 2 x 2 block at l
+            double g = (d[(size_t)l + 1] - d[(size_t)l]) / (2.0 * e[(size_t)l]);
+            double r = hypot(g, 1.0);
+            g = d[(size_t)m] - d[(size_t)l] + e[(size_t)l] / (g + (g >= 0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int64_t i = m - 1;
+            bool split = false;
+            for (; i >= l; --i) {
+                const double f = s * e[(size_t)i], b = c * e[(size_t)i];
+                r = hypot(f, g);
+                e[(size_t)i + 1] = r;
+                if (r == 0.0) {
+                    d[(size_t)i + 1] -= p;
+                    e[(size_t)m] = 0.0;
+                    split = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[(size_t)i + 1] - p;
+                r = (d[(size_t)i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[(size_t)i + 1] = g + p;
+                g = c * r - b;
+            }
+            if (split)
+                continue;
+            d[(size_t)l] -= p;
+            e[(size_t)l] = g;
+            e[(size_t)m] = 0.0;
+        }
+    }
+    std::sort(d.begin(), d.end());
+}
+
+// Newton steps on the normalised Hermite function phi_N at each zero, with
+// phi_N'(x) = sqrt(2N) phi_{N-1}(x) at a zero of phi_N (from the
+// derivative identity H_N' = 2N H_{N-1}); values through the three-term
+// recurrence of eq. (receqg) divided by sqrt(2^n n!), rescaled against
+// overflow.  The zeros are symmetric about 0: the upper half is polished and
+// mirrored.
+void polish_zeros(int64_t N, std::vector<double> &x)
+{
+    std::vector<double> a((size_t)N), b((size_t)N);
+    for (int64_t n = 0; n < N; ++n) {
+        a[(size_t)n] = sqrt(2.0 / (double)(n + 1));
+        b[(size_t)n] = sqrt((double)n / (double)(n + 1));
+    }
+    for (int64_t k = N / 2; k < N; ++k) {
+        double xk = x[(size_t)k];
+        for (int it = 0; it < 3; ++it) {
+            double pm = 0.0, p = 1.0; // phi_{n-1}, phi_n up to a common factor
+            for (int64_t n = 0; n < N; ++n) {
+                const double pn = a[(size_t)n] * xk * p - b[(size_t)n] * pm;
+                pm = p;
+                p = pn;
+                if (fabs(p) > 0x1p400) {
+                    p *= 0x1p-400;
+                    pm *= 0x1p-400;
+                }
+            }
+            // p = phi_N, pm = phi_{N-1} (same factor)
+            if (pm == 0.0)
+                break;
+            const double dx = p / (sqrt(2.0 * (double)N) * pm);
+            xk -= dx;
+            if (fabs(dx) <= 1e-17 * (1.0 + fabs(xk)))
+                break;
+        }
+        x[(size_t)k] = xk;
+        x[(size_t)(N - 1 - k)] = -xk;
+    }
+    if (N % 2 == 1)
+        x[(size_t)(N / 2)] = 0.0;
+}
+
+// U[n][k] = (u_k)_n of eq. (ortvec), 0-based:
+//   (u_k)_n = (-1)^(N+k+1) phi_n(x_k) / (sqrt(N) phi_{N-1}(x_k)),
+// the normalisation being the Christoffel-Darboux sum
+// sum_n phi_n(x_k)^2 = N phi_{N-1}(x_k)^2 at a zero of phi_N.  Each column
+// runs the recurrence once, keeping a running power-of-two exponent per n so
+// that no earlier value is rescaled.
+void ortho_vectors(int64_t N, const std::vector<double> &x, double *U)
+{
+    std::vector<double> a((size_t)N), b((size_t)N), val((size_t)N);
+    std::vector<int> ex((size_t)N);
+    for (int64_t n = 0; n < N; ++n) {
+        a[(size_t)n] = sqrt(2.0 / (double)(n + 1));
+        b[(size_t)n] = sqrt((double)n / (double)(n + 1));
+    }
+    const double rn = 1.0 / sqrt((double)N);
+    for (int64_t k = 0; k < N; ++k) {
+        const double xk = x[(size_t)k];
+        double pm = 0.0, p = 1.0;
+        int e = 0;
+        val[0] = 1.0;
+        ex[0] = 0;
+        for (int64_t n = 0; n + 1 < N; ++n) {
+            double pn = a[(size_t)n] * xk * p - b[(size_t)n] * pm;
+            pm = p;
+            p = pn;
+            if (fabs(p) > 0x1p400) {
+                p *= 0x1p-400;
+                pm *= 0x1p-400;
+                ++e;
+            }
+            val[(size_t)n + 1] = p;
+            ex[(size_t)n + 1] = e;
+        }
+        const double last = val[(size_t)N - 1];
+        const int elast = ex[(size_t)N - 1];
+        const double sgn = ((N + k + 1) % 2 == 0) ? 1.0 : -1.0;
+        const double scale = sgn * rn / last;
+        for (int64_t n = 0; n < N; ++n)
+            U[(size_t)n * (size_t)N + (size_t)k] = ldexp(val[(size_t)n], 400 * (ex[(size_t)n] - elast)) * scale;
+    }
+}
+
+int host_nodes(int64_t N, std::vector<double> &x)
+{
+    if (N < 1 || N > XFT_MAX_N)
+        return LCT_ERR_UNSUPPORTED_N;
+    if (N == 1) {
+        x.assign(1, 0.0);
+        return LCT_OK;
+    }
+    tridiag_zeros(N, x);
+    polish_zeros(N, x);
+    return LCT_OK;
+}
+
+template <typename R>
+int upload(const double *h, int64_t N, void **dst)
+{
+    const size_t n2 = (size_t)N * (size_t)N;
+    std::vector<R> tmp(n2);
+    for (size_t i = 0; i < n2; ++i)
+        tmp[i] = (R)h[i];
+    if (hipMalloc(dst, n2 * sizeof(R)) != hipSuccess) {
+        *dst = nullptr;
+        return LCT_ERR_HIP;
+    }
+    if (hipMemcpy(*dst, tmp.data(), n2 * sizeof(R), hipMemcpyHostToDevice) != hipSuccess)
+        return LCT_ERR_HIP;
+    return LCT_OK;
+}
+
+template <typename R>
+hipError_t xft_launch(const xft_plan_s *p, double zr, double zi, const void *in, void *out, int64_t batch, void *ws,
+                      hipStream_t s)
+{
+    const int N = (int)p->N;
+    R *w = reinterpret_cast<R *>(ws);           // N complex weights
+    R *V = w + 2 * (size_t)((N + 1) & ~1);      // batch x N complex (16-byte aligned)
+    hipLaunchKernelGGL(k_xft_weights<R>, dim3((N + 255) / 256), dim3(256), 0, s, zr, zi, N, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int ncol = (N + XC - 1) / XC;
+    const int64_t nsig = (batch + XS - 1) / XS;
+    const int ntiles = (int)(nsig * ncol);
+    const size_t lds = xft_lds_bytes((int)sizeof(R));
+    if ((e = allow_lds((const void *)k_xft_gemm<R>, lds)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_xft_gemm<R>, dim3(ntiles), dim3(XTHREADS), lds, s, (const R *)in, (const R *)p->U, V,
+                       (const R *)w, N, batch, ncol, ntiles);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_xft_gemm<R>, dim3(ntiles), dim3(XTHREADS), lds, s, (const R *)V, (const R *)p->Ut,
+                       (R *)out, (const R *)nullptr, N, batch, ncol, ntiles);
+    return hipGetLastError();
+}
+
+size_t ws_bytes_of(int64_t N, bool fp64, int64_t batch)
+{
+    const size_t el = fp64 ? 16 : 8; // one complex value
+    return (size_t)((N + 1) & ~int64_t(1)) * el + (size_t)batch * (size_t)N * el;
+}
+
+} // namespace
+
+extern "C" {
+
+int xft_nodes(int64_t N, double *x)
+{
+    if (x == nullptr)
+        return LCT_ERR_ARG;
+    std::vector<double> v;
+    int rc = host_nodes(N, v);
+    if (rc)
+        return rc;
+    for (int64_t k = 0; k < N; ++k)
+        x[k] = v[(size_t)k];
+    return LCT_OK;
+}
+
+int xft_vectors(int64_t N, double *U)
+{
+    if (U == nullptr)
+        return LCT_ERR_ARG;
+    std::vector<double> v;
+    int rc = host_nodes(N, v);
+    if (rc)
+        return rc;
+    ortho_vectors(N, v, U);
+    return LCT_OK;
+}
+
+int xft_plan_create(xft_plan *out, int64_t N, lct_precision prec)
+{
+    if (out == nullptr)
+        return LCT_ERR_ARG;
+    *out = nullptr;
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
+    if (prec != LCT_FP32 && prec != LCT_FP64)
+        return LCT_ERR_ARG;
+    std::vector<double> x;
+    int rc = host_nodes(N, x);
+    if (rc)
+        return rc;
+    std::vector<double> U((size_t)N * (size_t)N), Ut((size_t)N * (size_t)N);
+    ortho_vectors(N, x, U.data());
+    for (int64_t n = 0; n < N; ++n)
+        for (int64_t k = 0; k < N; ++k)
+            Ut[(size_t)k * (size_t)N + (size_t)n] = U[(size_t)n * (size_t)N + (size_t)k];
+    xft_plan p = new (std::nothrow) xft_plan_s{N, (int)prec, nullptr, nullptr};
+    if (!p)
+        return LCT_ERR_ARG;
+    const bool fp64 = prec == LCT_FP64;
+    rc = fp64 ? upload<double>(U.data(), N, &p->U) : upload<float>(U.data(), N, &p->U);
+    if (!rc)
+        rc = fp64 ? upload<double>(Ut.data(), N, &p->Ut) : upload<float>(Ut.data(), N, &p->Ut);
+    if (rc) {
+        xft_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return LCT_OK;
+}
+
+void xft_plan_destroy(xft_plan p)
+{
+    if (!p)
+        return;
+    if (p->U)
+        (void)hipFree(p->U);
+    if (p->Ut)
+        (void)hipFree(p->Ut);
+    delete p;
+}
+
+size_t xft_workspace_size(int64_t N, lct_precision prec, int64_t batch)
+{
+    if (N < 1 || N > XFT_MAX_N || batch < 0 || (prec != LCT_FP32 && prec != LCT_FP64))
+        return 0;
+    return ws_bytes_of(N, prec == LCT_FP64, batch);
+}
+
+int xft_exec(xft_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch, void *ws,
+             size_t ws_bytes, hipStream_t stream)
+{
+    if (!p || batch < 0)
+        return LCT_ERR_ARG;
+    if (!isfinite(z_re) || !isfinite(z_im))
+        return LCT_ERR_ARG;
+    if (hypot(z_re, z_im) > 1.0 + 1e-12)
+        return LCT_ERR_DOMAIN;
+    if (batch == 0)
+        return LCT_OK;
+    const bool fp64 = p->prec == LCT_FP64;
+    const uintptr_t al = fp64 ? 16 : 8;
+    if (in == nullptr || out == nullptr || ((uintptr_t)in) % al || ((uintptr_t)out) % al)
+        return LCT_ERR_ARG;
+    if (ws == nullptr || ((uintptr_t)ws) % 16 || ws_bytes < ws_bytes_of(p->N, fp64, batch))
+        return LCT_ERR_WORKSPACE;
+    if ((batch + XS - 1) / XS * ((p->N + XC - 1) / XC) > INT32_MAX)
+        return LCT_ERR_ARG;
+    const hipError_t e = fp64 ? xft_launch<double>(p, z_re, z_im, in, out, batch, ws, stream)
+                              : xft_launch<float>(p, z_re, z_im, in, out, batch, ws, stream);
+    return e == hipSuccess ? LCT_OK : LCT_ERR_HIP;
+}
+
+} // extern "C"

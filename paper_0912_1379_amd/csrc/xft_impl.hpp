@@ -1,0 +1,233 @@
+// xft_impl.hpp - the exact-node discrete fractional transform of eq. (tmat),
+//   g = sqrt(2 pi) U^T D(z) U f,  D(z) = diag(1, z, ..., z^(N-1)),
+// for a batch of signals sampled at the zeros of H_N, as two dense products on
+// the matrix cores:
+//   pass 1:  V[s][n] = w_n sum_k f[s][k] U[n][k],   w_n = sqrt(2 pi) z^n
+//   pass 2:  g[s][j] =     sum_n V[s][n] U[n][j] = sum_n V[s][n] Ut[j][n]
+// Both are C = diag-scaled (A B^T) with A complex (signals x K, interleaved)
+// and B real (columns x K, K contiguous): U for pass 1, its transpose Ut for
+// pass 2, so that both read B along K.  A complex row is two real rows of the
+// product (real and imaginary parts), so the matrix cores see a real GEMM of
+// 2 batch x N by N x N.
+//
+// MFMA: v_mfma_{f64,f32}_16x16x4 (D 16x16 += A 16x4 B 4x16).  Lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the results sit differently
+// (both read off the device with in-bounds probes): FP32 lane l, register r
+// holds D[4 (l / 16) + r][l % 16], FP64 holds D[(l / 16) + 4 r][l % 16].  A
+// 16-row block holds 8 signals' real (p = 0) and imaginary (p = 1) parts, at
+// row 2 s + p for FP32 and s + 8 p for FP64, so that in both cases a lane
+// ends with whole complex values of two signals (XLayout).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+#include "lct_params.hpp"
+
+namespace lctk {
+
+template <typename R> struct XMma;
+template <> struct XMma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct XMma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename R> struct XLayout;
+template <> struct XLayout<float> {
+    // row of (signal s < 8, part p) in a 16-row block
+    static __device__ __forceinline__ int row(int s, int p) { return 2 * s + p; }
+    // lane group g = l / 16, h < 2: signal and the registers of its parts
+    static __device__ __forceinline__ int sig(int g, int h) { return 2 * g + h; }
+    static constexpr int re(int h) { return 2 * h; }
+    static constexpr int im(int h) { return 2 * h + 1; }
+};
+template <> struct XLayout<double> {
+    static __device__ __forceinline__ int row(int s, int p) { return s + 8 * p; }
+    static __device__ __forceinline__ int sig(int g, int h) { return g + 4 * h; }
+    static constexpr int re(int h) { return h; }
+    static constexpr int im(int h) { return h + 2; }
+};
+
+// Work-group tile: XS signals (2 XS product rows) x XC columns, K in steps of
+// XK; 256 threads = 4 waves as 2 x 2, each wave XS rows x XC/2 columns.
+constexpr int XS = 64, XC = 128, XK = 16, XPAD = 1;
+constexpr int XTHREADS = 256;
+constexpr int XA_LD = XK + XPAD; // LDS row stride (elements)
+
+__host__ __device__ constexpr size_t xft_lds_bytes(int esize) { return (size_t)(2 * XS + XC) * XA_LD * esize; }
+
+// C[s][n] = scale[n] * sum_k A[s][k] Bm[n][k]   (scale may be null: 1)
+// A: batch x K complex, Bm: Ncol x K real, C: batch x Ncol complex, all
+// row-major and dense; K = Ncol = N here.
+template <typename R>
+__global__ __launch_bounds__(XTHREADS) void k_xft_gemm(const R *__restrict__ A, const R *__restrict__ Bm,
+                                                       R *__restrict__ C, const R *__restrict__ scale, int N,
+                                                       int64_t batch, int ncol_tiles, int ntiles)
+{
+    using acc_t = typename XMma<R>::acc_t;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *As = reinterpret_cast<R *>(smem_raw); // [2 XS][XA_LD]
+    R *Bs = As + 2 * XS * XA_LD;             // [XC][XA_LD]
+
+    // signal-major logical tiles; each XCD takes a contiguous range, so the
+    // work-groups that share a signal tile share one L2
+    const int tile = xcd_remap((int)blockIdx.x, ntiles);
+    const int st = tile / ncol_tiles, ct = tile - st * ncol_tiles;
+    const int64_t s0 = (int64_t)st * XS;
+    const int n0 = ct * XC;
+
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int wrow = (wave >> 1) * XS;       // first product row of this wave (of 2 XS)
+    const int wcol = (wave & 1) * (XC / 2);  // first column of this wave (of XC)
+
+    // global -> register staging: A as 64 signals x 4 threads x 4 complex,
+    // B as 128 columns x 2 threads x 8 reals
+    const int as_ = tid >> 2, ak = (tid & 3) * 4;
+    const int bn = tid >> 1, bk = (tid & 1) * 8;
+    const bool a_live = s0 + as_ < batch;
+    const bool b_live = n0 + bn < N;
+    const R *arow = A + (size_t)(a_live ? s0 + as_ : 0) * 2 * (size_t)N;
+    const R *brow = Bm + (size_t)(b_live ? n0 + bn : 0) * (size_t)N;
+
+    R ra[8], rb[8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + ak + q;
+            const bool ok = a_live && k < N;
+            ra[2 * q] = ok ? arow[2 * k] : (R)0;
+            ra[2 * q + 1] = ok ? arow[2 * k + 1] : (R)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = k0 + bk + q;
+            rb[q] = (b_live && k < N) ? brow[k] : (R)0;
+        }
+    };
+    const int arow_re = 16 * (as_ >> 3) + XLayout<R>::row(as_ & 7, 0);
+    const int arow_im = 16 * (as_ >> 3) + XLayout<R>::row(as_ & 7, 1);
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            As[arow_re * XA_LD + ak + q] = ra[2 * q];
+            As[arow_im * XA_LD + ak + q] = ra[2 * q + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            Bs[bn * XA_LD + bk + q] = rb[q];
+    };
+
+    constexpr int RB = XS / 16, CB = XC / 32; // 16 x 16 blocks per wave
+    acc_t acc[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+            acc[i][j] = acc_t{(R)0, (R)0, (R)0, (R)0};
+
+    fetch(0);
+    for (int k0 = 0; k0 < N; k0 += XK) {
+        __syncthreads(); // the previous step's reads of LDS are done
+        stash();
+        __syncthreads();
+        if (k0 + XK < N)
+            fetch(k0 + XK); // next tile in flight during the products
+#pragma unroll
+        for (int kk = 0; kk < XK; kk += 4) {
+            R a[RB], b[CB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                a[i] = As[(wrow + 16 * i + li) * XA_LD + kk + lg];
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+                b[j] = Bs[(wcol + 16 * j + li) * XA_LD + kk + lg];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < CB; ++j)
+                    acc[i][j] = XMma<R>::mma(a[i], b[j], acc[i][j]);
+        }
+    }
+
+    // epilogue: block i holds signals wrow / 2 + 8 i + (0 .. 7); this lane
+    // has two of them whole; column n = n0 + wcol + 16 j + li
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        const int n = n0 + wcol + 16 * j + li;
+        if (n >= N)
+            continue;
+        R wr = (R)1, wi = (R)0;
+        if (scale != nullptr) {
+            wr = scale[2 * n];
+            wi = scale[2 * n + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t s = s0 + wrow / 2 + 8 * i + XLayout<R>::sig(lg, h);
+                if (s >= batch)
+                    continue;
+                const R xr = acc[i][j][XLayout<R>::re(h)], xi = acc[i][j][XLayout<R>::im(h)];
+                R *dst = C + ((size_t)s * (size_t)N + (size_t)n) * 2;
+                dst[0] = xr * wr - xi * wi;
+                dst[1] = xr * wi + xi * wr;
+            }
+        }
+    }
+}
+
+// Complex double-double helpers for the powers of z.
+__device__ __forceinline__ DD xdd_add(DD a, DD b)
+{
+#pragma clang fp contract(off)
+    const double s = a.hi + b.hi;
+    const double bb = s - a.hi;
+    const double e = (a.hi - (s - bb)) + (b.hi - bb) + a.lo + b.lo;
+    return dd_quick(s, e);
+}
+__device__ __forceinline__ DD xdd_neg(DD a) { return DD{-a.hi, -a.lo}; }
+struct CDD {
+    DD re, im;
+};
+__device__ __forceinline__ CDD xcdd_mul(const CDD &x, const CDD &y)
+{
+    return CDD{xdd_add(dd_mul(x.re, y.re), xdd_neg(dd_mul(x.im, y.im))),
+               xdd_add(dd_mul(x.re, y.im), dd_mul(x.im, y.re))};
+}
+
+// w[n] = sqrt(2 pi) z^n, n < N, by binary powering in double-double (about
+// 2 log2(n) products, each with relative error near 2^-104), rounded once.
+template <typename R>
+__global__ void k_xft_weights(double zr, double zi, int N, R *__restrict__ w)
+{
+    const int n = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (n >= N)
+        return;
+    CDD acc{DD{1.0, 0.0}, DD{0.0, 0.0}};
+    CDD base{DD{zr, 0.0}, DD{zi, 0.0}};
+    for (int e = n; e > 0; e >>= 1) {
+        if (e & 1)
+            acc = xcdd_mul(acc, base);
+        if (e > 1)
+            base = xcdd_mul(base, base);
+    }
+    const DD s2pi{2.5066282746310007, -1.8328579980459167e-16}; // sqrt(2 pi), double-double
+    const DD wr = dd_mul(acc.re, s2pi), wi = dd_mul(acc.im, s2pi);
+    w[2 * n] = (R)(wr.hi + wr.lo);
+    w[2 * n + 1] = (R)(wi.hi + wi.lo);
+}
+
+} // namespace lctk

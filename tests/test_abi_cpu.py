@@ -20,7 +20,7 @@ def declared_functions():
     src = open(_lib.HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", src, flags=re.M)
-    return sorted(set(n for n in names if n.startswith(("lct_", "frft_"))))
+    return sorted(set(n for n in names if n.startswith(("lct_", "frft_", "xft_"))))
 
 
 def test_header_declares_the_bound_functions():
@@ -129,6 +129,38 @@ def test_scaled_nodes_helper_matches_oracle(lib, N, b, d, s):
     assert np.allclose(y, oracle.output_nodes(N, b, d, scale=s), rtol=1e-15, atol=1e-13)
     assert lib.lct_nodes_scaled(N, b, d, 0.0, None, None) == _lib.LCT_ERR_ARG
     assert lib.lct_nodes_scaled(N, b, d, float("nan"), None, None) == _lib.LCT_ERR_ARG
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 511])
+def test_xft_host_nodes_and_vectors_match_oracle(lib, N):
+    """The library's exact nodes (QL + Newton) and eq. (ortvec) vectors (recurrence with
+    Christoffel-Darboux normalisation) against the oracle's (Sturm bisection, explicit sums)."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    x = np.empty(N)
+    U = np.empty((N, N))
+    assert lib.xft_nodes(N, x.ctypes.data_as(dp)) == 0
+    assert lib.xft_vectors(N, U.ctypes.data_as(dp)) == 0
+    assert np.abs(x - oracle.hermite_zeros(N)).max() <= 1e-14 * max(1.0, np.abs(x).max())
+    assert np.abs(U - oracle.hermite_vectors(N)).max() <= 1e-13
+
+
+def test_xft_argument_errors(lib):
+    h = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.xft_plan_create(ctypes.byref(h), 64, 2) == _lib.LCT_ERR_UNSUPPORTED
+    assert lib.xft_plan_create(ctypes.byref(h), 64, 7) == _lib.LCT_ERR_ARG
+    assert lib.xft_plan_create(ctypes.byref(h), 0, 0) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert lib.xft_plan_create(ctypes.byref(h), 16385, 0) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert lib.xft_plan_create(None, 64, 0) == _lib.LCT_ERR_ARG
+    assert not h.value
+    assert lib.xft_exec(None, 0.5, 0.0, 8, 16, 1, 32, 1 << 20, None) == _lib.LCT_ERR_ARG
+    assert lib.xft_nodes(0, np.empty(1).ctypes.data_as(dp)) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert lib.xft_nodes(8, None) == _lib.LCT_ERR_ARG
+    # workspace: N complex weights (rounded up to even) + batch x N complex
+    assert lib.xft_workspace_size(100, 0, 3) == (100 + 300) * 8
+    assert lib.xft_workspace_size(101, 1, 3) == (102 + 303) * 16
+    assert lib.xft_workspace_size(100, 2, 3) == 0
+    lib.xft_plan_destroy(None)
 
 
 # --- autotuner table (host functions only) ------------------------------------

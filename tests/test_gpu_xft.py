@@ -1,0 +1,116 @@
+"""GPU parity of the exact-node discrete fractional transform of eq. (tmat):
+xft_exec (two matrix-core passes through the C ABI) against the oracle's
+sqrt(2 pi) U^T D(z) U f, element by element on the same seeded inputs sampled
+at the zeros of H_N.
+
+Bounds: relative L2 error per signal <= 1e-12 for FP64 and <= 2e-5 for FP32
+(the bounds of the method's FP64 / FP32 variants); the FP32 path rounds U to
+FP32 and accumulates N products in FP32, about 1e-6 here.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_0912_1379_amd as lct
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 2e-5, torch.complex128: 1e-12}
+PREC = {torch.complex64: lct.LCT_FP32, torch.complex128: lct.LCT_FP64}
+ZS = [0.7 * np.exp(0.9j), 1j, -1.0, 1.0, 0.3, -0.55 + 0.3j]
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
+
+
+def inputs(N, batch, seed):
+    g = np.random.default_rng(seed)
+    gp = workloads.gaussian_params(batch, g)
+    return workloads.chirped_gaussians(oracle.hermite_zeros(N), gp)
+
+
+_PLANS = {}
+
+
+def plan_of(N, dtype):
+    key = (N, dtype)
+    if key not in _PLANS:
+        _PLANS[key] = lct.xft_plan_create(N, PREC[dtype])
+    return _PLANS[key]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("N,batch", [(1, 3), (2, 1), (3, 5), (17, 70), (100, 64), (128, 65), (257, 9),
+                                     (1000, 33)])
+def test_xft_matches_oracle(dtype, N, batch):
+    print(f"[xft] N={N} batch={batch} {dtype}", flush=True)
+    f = inputs(N, batch, 900 + N)
+    x = dev(f, dtype)
+    fin = x.cpu().numpy().astype(np.complex128)
+    U = oracle.hermite_vectors(N)
+    p = plan_of(N, dtype)
+    for z in ZS:
+        y = lct.xft_exec(p, z, x).cpu().numpy().astype(np.complex128)
+        ref = oracle.xft(fin, z, U)
+        e = rel_rows(y, ref)
+        assert e.max() <= TOL[dtype], (N, batch, z, e.max())
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_xft_full_size_rows(dtype):
+    """N = 4096 (the batched configuration's length), 96 signals, every output."""
+    N, batch = 4096, 96
+    print(f"[xft] N={N} batch={batch} {dtype}", flush=True)
+    x = dev(inputs(N, batch, 77), dtype)
+    fin = x.cpu().numpy().astype(np.complex128)
+    U = oracle.hermite_vectors(N)
+    p = plan_of(N, dtype)
+    z = 0.8 * np.exp(-0.6j)
+    y = lct.xft_exec(p, z, x).cpu().numpy().astype(np.complex128)
+    e = rel_rows(y, oracle.xft(fin, z, U))
+    assert e.max() <= TOL[dtype], e.max()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_xft_eigenvectors(dtype):
+    """Rows of U are eigenvectors: F_z U[n] = sqrt(2 pi) z^n U[n] (U from the oracle)."""
+    N = 300
+    U = oracle.hermite_vectors(N)
+    rows = [0, 1, 2, 50, 151, 299]
+    x = dev(U[rows].astype(np.complex128), dtype)
+    z = np.exp(0.41j)
+    y = lct.xft_exec(plan_of(N, dtype), z, x).cpu().numpy().astype(np.complex128)
+    ref = np.stack([np.sqrt(2 * np.pi) * z ** n * U[n] for n in rows])
+    assert rel_rows(y, ref).max() <= 4 * TOL[dtype]
+
+
+def test_xft_in_place_and_errors():
+    N, batch = 200, 7
+    x = dev(inputs(N, batch, 5), torch.complex128)
+    p = plan_of(N, torch.complex128)
+    y = lct.xft_exec(p, 0.6j, x)
+    x2 = x.clone()
+    lct.xft_exec(p, 0.6j, x2, out=x2)
+    assert torch.equal(x2, y)
+    with pytest.raises(lct.LctError):
+        lct.xft_exec(p, 1.2, x)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lct.LctError):
+        lct.xft_exec(p, 0.5, x, ws=small)
+    with pytest.raises(TypeError):
+        lct.xft_exec(p, 0.5, x.to(torch.complex64))
+    empty = torch.empty(0, N, dtype=torch.complex128, device="cuda")
+    assert lct.xft_exec(p, 0.5, empty).shape == (0, N)
