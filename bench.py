@@ -347,6 +347,77 @@ def frft_errors(out, x, y, ysh, z, N):
         out["shared_order"]["rel_l2_max"] = max(esh)
 
 
+PEAK_MFMA_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def bench_xft(args):
+    """Exact-node discrete fractional transform of eq. (tmat) on the matrix
+    cores: 4096 signals x N = 4096 sampled at the zeros of H_N, one order z
+    for the batch; FP32 (the step) and FP64 legs.  One call = a weights
+    kernel and two GEMM passes, 8 B N^2 flops."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+
+    B, N = args.signals, args.N
+    g = workloads.rng(5)
+    gp = workloads.gaussian_params(B, g)
+    xe = lct.xft_nodes(N)
+    f = workloads.chirped_gaussians(xe, gp)
+    z = 0.8 * np.exp(-0.6j)
+    flops = 8.0 * B * N * N
+    legs = {}
+    outs = {}
+    for name, prec, dt in [("f32", lct.LCT_FP32, torch.complex64), ("f64", lct.LCT_FP64, torch.complex128)]:
+        if name == "f64" and args.no_fp64:
+            continue
+        plan = lct.xft_plan_create(N, prec)
+        x = torch.from_numpy(f).to("cuda").to(dt)
+        y = torch.empty_like(x)
+        ws = torch.empty(lct.xft_workspace_size(N, prec, B), dtype=torch.uint8, device="cuda")
+        steps = args.steps if name == "f32" else max(3, args.steps // 2)
+        ms, ms_kernel, wall = time_launches(lambda: lct.xft_exec(plan, z, x, out=y, ws=ws), steps, args.warmup)
+        tf = flops / (ms_kernel * 1e-3) / 1e12
+        legs[name] = {"ms_per_step": ms, "kernel_ms": ms_kernel, "TFLOPs": tf, "steps": steps, "wall_s_timed": wall,
+                      "frac": tf / PEAK_MFMA_TFLOPS[name]}
+        outs[name] = (x, y)
+        print(f"[bench] xft {name}: {ms:.3f} ms/step, {tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    main = legs["f32"]
+    out = {
+        "metric": "complex samples/s, exact-node discrete fractional transform (eq. tmat) on the matrix cores",
+        "value": B * N / (main["ms_per_step"] * 1e-3), "unit": "complex samples/s", "n_gpus": 1,
+        "steps": main["steps"], "warmup": args.warmup, "ms_per_step": main["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"exact-node transform, {B} signals x N={N} complex64 at the zeros of H_N, "
+                               "one order z for the batch", "signals": B, "N": N},
+        "roofline": {"bound": "mfma", "achieved": main["TFLOPs"], "peak": PEAK_MFMA_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": main["frac"], "traffic": None,
+                     "kernel": "k_xft_gemm<float> x 2 (+ k_xft_weights)", "kernel_ms": main["kernel_ms"],
+                     "algorithmic_flops_per_call": flops},
+        "wall_s_timed": main["wall_s_timed"], "fp64_path": legs.get("f64"),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        t0 = time.perf_counter()
+        U = oracle.hermite_vectors(N)
+        nb = 64
+        ref = oracle.xft(f[:nb], z, U)
+        el = time.perf_counter() - t0
+        errs = {}
+        for name, (x, y) in outs.items():
+            fin = x[:nb].cpu().numpy().astype(np.complex128)
+            r = oracle.xft(fin, z, U)
+            got = y[:nb].cpu().numpy().astype(np.complex128)
+            errs[name] = float((np.linalg.norm(got - r, axis=1) / np.linalg.norm(r, axis=1)).max())
+        out["rel_l2"] = errs
+        out["cpu_baseline"] = {"value": nb * N / el, "unit": "complex samples/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{nb} of the {B} signals (U of eq. ortvec in long "
+                                                           f"double, then numpy products), {el:.1f} s"}
+        del ref
+    return out
+
+
 def bench_fit(args):
     """Differentiable LCT fit: 256 signals x N = 2048 complex64, loss
     ||abs(LCT_M(f))^2 - I_target||^2 with I_target from a hidden matrix; one
@@ -402,9 +473,10 @@ def main():
                     help="frft workload: skip the shared-order (precomputed kernel spectrum) leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
-    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft"], default="batched",
+    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft", "xft"], default="batched",
                     help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
-                         "large: 16 x 2^20; fit: autograd step at 256 x 2048; frft: 4096 x N=4096 fractional")
+                         "large: 16 x 2^20; fit: autograd step at 256 x 2048; frft: 4096 x N=4096 fractional; "
+                         "xft: 4096 x N=4096 exact-node transform on the matrix cores")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -414,7 +486,8 @@ def main():
         sys.exit(2)
 
     if args.workload != "batched":
-        fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit, "frft": bench_frft}[args.workload]
+        fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit, "frft": bench_frft,
+              "xft": bench_xft}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

@@ -59,7 +59,11 @@ template <> struct XLayout<double> {
 };
 
 // Work-group tile: XS signals (2 XS product rows) x XC columns, K in steps of
-// XK; 256 threads = 4 waves as 2 x 2, each wave XS rows x XC/2 columns.
+// XK; 256 threads = 4 waves as 2 x 2, each wave XS rows x XC/2 columns.  The
+// launch bound asks for two work-groups per CU (at most 256 registers per
+// lane): at one wave per SIMD the FP64 products stalled at every barrier.
+// Measured at 4096 x 4096 against this shape: K steps of 32, and two LDS
+// buffers with one barrier per step, were both slower.
 constexpr int XS = 64, XC = 128, XK = 16, XPAD = 1;
 constexpr int XTHREADS = 256;
 constexpr int XA_LD = XK + XPAD; // LDS row stride (elements)
@@ -70,7 +74,7 @@ __host__ __device__ constexpr size_t xft_lds_bytes(int esize) { return (size_t)(
 // A: batch x K complex, Bm: Ncol x K real, C: batch x Ncol complex, all
 // row-major and dense; K = Ncol = N here.
 template <typename R>
-__global__ __launch_bounds__(XTHREADS) void k_xft_gemm(const R *__restrict__ A, const R *__restrict__ Bm,
+__global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm(const R *__restrict__ A, const R *__restrict__ Bm,
                                                        R *__restrict__ C, const R *__restrict__ scale, int N,
                                                        int64_t batch, int ncol_tiles, int ntiles)
 {
@@ -92,26 +96,28 @@ __global__ __launch_bounds__(XTHREADS) void k_xft_gemm(const R *__restrict__ A, 
     const int wrow = (wave >> 1) * XS;       // first product row of this wave (of 2 XS)
     const int wcol = (wave & 1) * (XC / 2);  // first column of this wave (of XC)
 
-    // global -> register staging: A as 64 signals x 4 threads x 4 complex,
-    // B as 128 columns x 2 threads x 8 reals
-    const int as_ = tid >> 2, ak = (tid & 3) * 4;
-    const int bn = tid >> 1, bk = (tid & 1) * 8;
+    // global -> register staging: A as XS signals x 4 threads x AQ complex,
+    // B as XC columns x 2 threads x BQ reals
+    static_assert(XS * 4 == XTHREADS && XC * 2 == XTHREADS, "staging covers the tile");
+    constexpr int AQ = XK / 4, BQ = XK / 2;
+    const int as_ = tid >> 2, ak = (tid & 3) * AQ;
+    const int bn = tid >> 1, bk = (tid & 1) * BQ;
     const bool a_live = s0 + as_ < batch;
     const bool b_live = n0 + bn < N;
     const R *arow = A + (size_t)(a_live ? s0 + as_ : 0) * 2 * (size_t)N;
     const R *brow = Bm + (size_t)(b_live ? n0 + bn : 0) * (size_t)N;
 
-    R ra[8], rb[8];
+    R ra[2 * AQ], rb[BQ];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < AQ; ++q) {
             const int k = k0 + ak + q;
             const bool ok = a_live && k < N;
             ra[2 * q] = ok ? arow[2 * k] : (R)0;
             ra[2 * q + 1] = ok ? arow[2 * k + 1] : (R)0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < BQ; ++q) {
             const int k = k0 + bk + q;
             rb[q] = (b_live && k < N) ? brow[k] : (R)0;
         }
@@ -120,12 +126,12 @@ __global__ __launch_bounds__(XTHREADS) void k_xft_gemm(const R *__restrict__ A, 
     const int arow_im = 16 * (as_ >> 3) + XLayout<R>::row(as_ & 7, 1);
     auto stash = [&]() {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < AQ; ++q) {
             As[arow_re * XA_LD + ak + q] = ra[2 * q];
             As[arow_im * XA_LD + ak + q] = ra[2 * q + 1];
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < BQ; ++q)
             Bs[bn * XA_LD + bk + q] = rb[q];
     };
 
