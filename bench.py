@@ -368,8 +368,9 @@ def bench_xft(args):
     flops = 8.0 * B * N * N
     legs = {}
     outs = {}
-    for name, prec, dt in [("f32", lct.LCT_FP32, torch.complex64), ("f64", lct.LCT_FP64, torch.complex128)]:
-        if name == "f64" and args.no_fp64:
+    for name, prec, dt in [("f32", lct.LCT_FP32, torch.complex64), ("f64", lct.LCT_FP64, torch.complex128),
+                           ("splitbf16", lct.LCT_FP32_SPLITBF16, torch.complex64)]:
+        if (name == "f64" and args.no_fp64) or (name == "splitbf16" and args.no_split):
             continue
         plan = lct.xft_plan_create(N, prec)
         x = torch.from_numpy(f).to("cuda").to(dt)
@@ -378,8 +379,13 @@ def bench_xft(args):
         steps = args.steps if name == "f32" else max(3, args.steps // 2)
         ms, ms_kernel, wall = time_launches(lambda: lct.xft_exec(plan, z, x, out=y, ws=ws), steps, args.warmup)
         tf = flops / (ms_kernel * 1e-3) / 1e12
-        legs[name] = {"ms_per_step": ms, "kernel_ms": ms_kernel, "TFLOPs": tf, "steps": steps, "wall_s_timed": wall,
-                      "frac": tf / PEAK_MFMA_TFLOPS[name]}
+        legs[name] = {"ms_per_step": ms, "kernel_ms": ms_kernel, "TFLOPs": tf, "steps": steps, "wall_s_timed": wall}
+        if name in PEAK_MFMA_TFLOPS:
+            legs[name]["frac"] = tf / PEAK_MFMA_TFLOPS[name]
+        else:
+            # three BF16 products per term: matrix-core rate against the 2.5 PFLOP/s BF16 peak
+            legs[name]["bf16_TFLOPs"] = 3 * tf
+            legs[name]["frac_of_bf16_peak"] = 3 * tf / 2500.0
         outs[name] = (x, y)
         print(f"[bench] xft {name}: {ms:.3f} ms/step, {tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
     main = legs["f32"]
@@ -394,7 +400,7 @@ def bench_xft(args):
                      "frac": main["frac"], "traffic": None,
                      "kernel": "k_xft_gemm<float> x 2 (+ k_xft_weights)", "kernel_ms": main["kernel_ms"],
                      "algorithmic_flops_per_call": flops},
-        "wall_s_timed": main["wall_s_timed"], "fp64_path": legs.get("f64"),
+        "wall_s_timed": main["wall_s_timed"], "fp64_path": legs.get("f64"), "splitbf16_path": legs.get("splitbf16"),
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -274,14 +274,17 @@ void lct_tune_clear(void);
  *   out[s] = F_z in[s],  F_z = sqrt(2 pi) U^T D(z) U,  D(z) = diag(1, z, ..., z^(N-1)),
  * U the orthogonal matrix of eq. (ortvec), U[n][k] = (u_k)_n.  This is the
  * O(N^2)-per-signal method the fast transforms approximate; it is evaluated as
- * two dense products on the matrix cores (FP64 or FP32 arithmetic by the
- * plan's precision; LCT_FP32_SPLITBF16 gives LCT_ERR_UNSUPPORTED), with the
- * weights sqrt(2 pi) z^n formed on the device in double-double.
+ * two dense products on the matrix cores, FP64 or FP32 arithmetic by the
+ * plan's precision; with LCT_FP32_SPLITBF16 the data are complex64 and the
+ * products run as BF16 hi + lo parts with FP32 accumulation (about 16
+ * significant bits per product).  The weights sqrt(2 pi) z^n are formed on
+ * the device in double-double.
  *
  * xft_plan_create computes the zeros (QL eigenvalues of the symmetric
  * tridiagonal H of §2, polished by Newton steps) and U (recurrence of eq.
  * receqg, normalised by the Christoffel-Darboux sum) on the host and keeps U
- * and U^T in plan-owned DEVICE memory (2 N^2 values of the plan's precision);
+ * and U^T in plan-owned DEVICE memory (2 N^2 values of the plan's precision,
+ * or their BF16 parts with rows padded to a multiple of 8);
  * 1 <= N <= 16384, any N.  xft_exec: in, out DEVICE batch x N complex (in ==
  * out allowed), |z| <= 1 (beyond 1e-12: LCT_ERR_DOMAIN), ws a caller-owned
  * DEVICE workspace of xft_workspace_size(N, prec, batch) bytes, 16-byte

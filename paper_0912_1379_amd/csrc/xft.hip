@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <new>
@@ -20,6 +21,9 @@ struct xft_plan_s {
     int prec;
     void *U;  // N x N, U[n][k] = (u_k)_n, in the plan's precision (device)
     void *Ut; // its transpose (device)
+    // split-BF16 plans: U and U^T as hi + lo BF16 parts, rows padded to ldb
+    void *Uh, *Ul, *Uth, *Utl;
+    int ldb;
 };
 
 namespace {
@@ -193,6 +197,71 @@ int upload(const double *h, int64_t N, void **dst)
     return LCT_OK;
 }
 
+// IEEE binary32 -> bfloat16, round to nearest even (finite inputs).
+uint16_t bf16_rne(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// hi = bf16(x), lo = bf16(x - hi) of every entry of the N x N matrix M,
+// rows padded with zeros to ldb; uploaded to two new device arrays.
+int upload_split(const double *M, int64_t N, int ldb, void **dh, void **dl)
+{
+    const size_t n = (size_t)N * (size_t)ldb;
+    std::vector<uint16_t> h(n, 0), l(n, 0);
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t c = 0; c < N; ++c) {
+            const double x = M[(size_t)r * (size_t)N + (size_t)c];
+            const uint16_t hb = bf16_rne((float)x);
+            h[(size_t)r * ldb + (size_t)c] = hb;
+            l[(size_t)r * ldb + (size_t)c] = bf16_rne((float)(x - (double)bf16_value(hb)));
+        }
+    *dh = *dl = nullptr;
+    if (hipMalloc(dh, n * 2) != hipSuccess || hipMalloc(dl, n * 2) != hipSuccess)
+        return LCT_ERR_HIP;
+    if (hipMemcpy(*dh, h.data(), n * 2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(*dl, l.data(), n * 2, hipMemcpyHostToDevice) != hipSuccess)
+        return LCT_ERR_HIP;
+    return LCT_OK;
+}
+
+hipError_t xft_launch_sb(const xft_plan_s *p, double zr, double zi, const void *in, void *out, int64_t batch,
+                         void *ws, hipStream_t s)
+{
+    const int N = (int)p->N;
+    float *w = reinterpret_cast<float *>(ws);
+    float *V = w + 2 * (size_t)((N + 1) & ~1);
+    hipLaunchKernelGGL(k_xft_weights<float>, dim3((N + 255) / 256), dim3(256), 0, s, zr, zi, N, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int ncol = (N + XC - 1) / XC;
+    const int ntiles = (int)((batch + XS - 1) / XS * ncol);
+    const size_t lds = xft_sb_lds_bytes();
+    if ((e = allow_lds((const void *)k_xft_gemm_sb, lds)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_xft_gemm_sb, dim3(ntiles), dim3(XTHREADS), lds, s, (const float *)in,
+                       (const __bf16 *)p->Uh, (const __bf16 *)p->Ul, V, (const float *)w, N, p->ldb, batch, ncol,
+                       ntiles);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_xft_gemm_sb, dim3(ntiles), dim3(XTHREADS), lds, s, (const float *)V,
+                       (const __bf16 *)p->Uth, (const __bf16 *)p->Utl, (float *)out, (const float *)nullptr, N,
+                       p->ldb, batch, ncol, ntiles);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t xft_launch(const xft_plan_s *p, double zr, double zi, const void *in, void *out, int64_t batch, void *ws,
                       hipStream_t s)
@@ -259,9 +328,7 @@ int xft_plan_create(xft_plan *out, int64_t N, lct_precision prec)
     if (out == nullptr)
         return LCT_ERR_ARG;
     *out = nullptr;
-    if (prec == LCT_FP32_SPLITBF16)
-        return LCT_ERR_UNSUPPORTED;
-    if (prec != LCT_FP32 && prec != LCT_FP64)
+    if (prec != LCT_FP32 && prec != LCT_FP64 && prec != LCT_FP32_SPLITBF16)
         return LCT_ERR_ARG;
     std::vector<double> x;
     int rc = host_nodes(N, x);
@@ -272,13 +339,20 @@ int xft_plan_create(xft_plan *out, int64_t N, lct_precision prec)
     for (int64_t n = 0; n < N; ++n)
         for (int64_t k = 0; k < N; ++k)
             Ut[(size_t)k * (size_t)N + (size_t)n] = U[(size_t)n * (size_t)N + (size_t)k];
-    xft_plan p = new (std::nothrow) xft_plan_s{N, (int)prec, nullptr, nullptr};
+    xft_plan p = new (std::nothrow) xft_plan_s{N, (int)prec, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     if (!p)
         return LCT_ERR_ARG;
     const bool fp64 = prec == LCT_FP64;
-    rc = fp64 ? upload<double>(U.data(), N, &p->U) : upload<float>(U.data(), N, &p->U);
-    if (!rc)
-        rc = fp64 ? upload<double>(Ut.data(), N, &p->Ut) : upload<float>(Ut.data(), N, &p->Ut);
+    if (prec == LCT_FP32_SPLITBF16) {
+        p->ldb = (int)((N + 7) / 8 * 8);
+        rc = upload_split(U.data(), N, p->ldb, &p->Uh, &p->Ul);
+        if (!rc)
+            rc = upload_split(Ut.data(), N, p->ldb, &p->Uth, &p->Utl);
+    } else {
+        rc = fp64 ? upload<double>(U.data(), N, &p->U) : upload<float>(U.data(), N, &p->U);
+        if (!rc)
+            rc = fp64 ? upload<double>(Ut.data(), N, &p->Ut) : upload<float>(Ut.data(), N, &p->Ut);
+    }
     if (rc) {
         xft_plan_destroy(p);
         return rc;
@@ -295,12 +369,15 @@ void xft_plan_destroy(xft_plan p)
         (void)hipFree(p->U);
     if (p->Ut)
         (void)hipFree(p->Ut);
+    for (void *q : {p->Uh, p->Ul, p->Uth, p->Utl})
+        if (q)
+            (void)hipFree(q);
     delete p;
 }
 
 size_t xft_workspace_size(int64_t N, lct_precision prec, int64_t batch)
 {
-    if (N < 1 || N > XFT_MAX_N || batch < 0 || (prec != LCT_FP32 && prec != LCT_FP64))
+    if (N < 1 || N > XFT_MAX_N || batch < 0 || (prec != LCT_FP32 && prec != LCT_FP64 && prec != LCT_FP32_SPLITBF16))
         return 0;
     return ws_bytes_of(N, prec == LCT_FP64, batch);
 }
@@ -325,7 +402,8 @@ int xft_exec(xft_plan p, double z_re, double z_im, const void *in, void *out, in
     if ((batch + XS - 1) / XS * ((p->N + XC - 1) / XC) > INT32_MAX)
         return LCT_ERR_ARG;
     const hipError_t e = fp64 ? xft_launch<double>(p, z_re, z_im, in, out, batch, ws, stream)
-                              : xft_launch<float>(p, z_re, z_im, in, out, batch, ws, stream);
+                         : p->prec == LCT_FP32_SPLITBF16 ? xft_launch_sb(p, z_re, z_im, in, out, batch, ws, stream)
+                                                         : xft_launch<float>(p, z_re, z_im, in, out, batch, ws, stream);
     return e == hipSuccess ? LCT_OK : LCT_ERR_HIP;
 }
 

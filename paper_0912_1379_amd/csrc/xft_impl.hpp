@@ -23,6 +23,7 @@
 
 #include "fft_core.hpp"
 #include "lct_params.hpp"
+#include "mfma_fft.hpp"
 
 namespace lctk {
 
@@ -188,6 +189,169 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm(const R *__restrict__ 
                     continue;
                 const R xr = acc[i][j][XLayout<R>::re(h)], xi = acc[i][j][XLayout<R>::im(h)];
                 R *dst = C + ((size_t)s * (size_t)N + (size_t)n) * 2;
+                dst[0] = xr * wr - xi * wi;
+                dst[1] = xr * wi + xi * wr;
+            }
+        }
+    }
+}
+
+// Split-BF16 variant for FP32 data: every operand x is held as x = hi + lo
+// with hi = bf16(x), lo = bf16(x - hi) (about 16 significant bits), and a
+// 16 x 16 block accumulates A_hi B_lo + A_lo B_hi + A_hi B_hi in FP32 with
+// v_mfma_f32_16x16x32_bf16 (the lo-lo term is below FP32 resolution).  Lane l
+// supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i < 8
+// (16 contiguous bytes of a K-contiguous LDS row each), and receives
+// D[4 (l / 16) + r][l % 16]: the FP32 row order, so the rows of a signal are
+// 2 s + p as in k_xft_gemm<float>.  The signals arrive in FP32 and are split
+// while staged into LDS; U is split once, at plan creation (Bh, Bl, rows
+// padded to ldb, a multiple of 8, with zeros, so that they load 16 bytes at
+// a time).
+constexpr int XSB_K = 64;             // K step (two MFMA K blocks of 32)
+constexpr int XSB_LD = XSB_K + 8;     // LDS row stride in bf16 (144 bytes)
+
+__host__ __device__ constexpr size_t xft_sb_lds_bytes() { return (size_t)2 * (2 * XS + XC) * XSB_LD * 2; }
+
+__global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__restrict__ A,
+                                                            const __bf16 *__restrict__ Bh,
+                                                            const __bf16 *__restrict__ Bl, float *__restrict__ C,
+                                                            const float *__restrict__ scale, int N, int ldb,
+                                                            int64_t batch, int ncol_tiles, int ntiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __bf16 *Ah = reinterpret_cast<__bf16 *>(smem_raw); // [2 XS][XSB_LD]
+    __bf16 *Al = Ah + 2 * XS * XSB_LD;
+    __bf16 *Bsh = Al + 2 * XS * XSB_LD; // [XC][XSB_LD]
+    __bf16 *Bsl = Bsh + XC * XSB_LD;
+
+    const int tile = xcd_remap((int)blockIdx.x, ntiles);
+    const int st = tile / ncol_tiles, ct = tile - st * ncol_tiles;
+    const int64_t s0 = (int64_t)st * XS;
+    const int n0 = ct * XC;
+
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int wrow = (wave >> 1) * XS;
+    const int wcol = (wave & 1) * (XC / 2);
+
+    // staging: A as XS signals x 4 threads x 16 complex; B as XC columns x
+    // 2 threads x 32 values of each of Bh, Bl
+    constexpr int AQ = XSB_K / 4, BQ = XSB_K / 2;
+    const int as_ = tid >> 2, ak = (tid & 3) * AQ;
+    const int bn = tid >> 1, bk = (tid & 1) * BQ;
+    const bool a_live = s0 + as_ < batch;
+    const bool b_live = n0 + bn < N;
+    const float *arow = A + (size_t)(a_live ? s0 + as_ : 0) * 2 * (size_t)N;
+    const __bf16 *bhrow = Bh + (size_t)(b_live ? n0 + bn : 0) * (size_t)ldb;
+    const __bf16 *blrow = Bl + (size_t)(b_live ? n0 + bn : 0) * (size_t)ldb;
+    const int arow_re = 16 * (as_ >> 3) + XLayout<float>::row(as_ & 7, 0);
+    const int arow_im = 16 * (as_ >> 3) + XLayout<float>::row(as_ & 7, 1);
+
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const float2 *acx = reinterpret_cast<const float2 *>(arow);
+    float2 ra[AQ];
+    u32x4 rbh[BQ / 8], rbl[BQ / 8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int k = k0 + ak + q;
+            ra[q] = (a_live && k < N) ? acx[k] : float2{0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int c = 0; c < BQ / 8; ++c) {
+            const int k = k0 + bk + 8 * c; // a multiple of 8: the chunk lies inside or beyond ldb
+            const bool ok = b_live && k < ldb;
+            rbh[c] = ok ? *reinterpret_cast<const u32x4 *>(bhrow + k) : u32x4{0u, 0u, 0u, 0u};
+            rbl[c] = ok ? *reinterpret_cast<const u32x4 *>(blrow + k) : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int c = 0; c < AQ / 8; ++c) {
+            bf16x8 hr, lr, hi_, li_;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __bf16 h, l;
+                split_bf16(ra[8 * c + q].x, h, l);
+                hr[q] = h;
+                lr[q] = l;
+                split_bf16(ra[8 * c + q].y, h, l);
+                hi_[q] = h;
+                li_[q] = l;
+            }
+            *reinterpret_cast<bf16x8 *>(Ah + arow_re * XSB_LD + ak + 8 * c) = hr;
+            *reinterpret_cast<bf16x8 *>(Al + arow_re * XSB_LD + ak + 8 * c) = lr;
+            *reinterpret_cast<bf16x8 *>(Ah + arow_im * XSB_LD + ak + 8 * c) = hi_;
+            *reinterpret_cast<bf16x8 *>(Al + arow_im * XSB_LD + ak + 8 * c) = li_;
+        }
+#pragma unroll
+        for (int c = 0; c < BQ / 8; ++c) {
+            *reinterpret_cast<u32x4 *>(Bsh + bn * XSB_LD + bk + 8 * c) = rbh[c];
+            *reinterpret_cast<u32x4 *>(Bsl + bn * XSB_LD + bk + 8 * c) = rbl[c];
+        }
+    };
+
+    constexpr int RB = XS / 16, CB = XC / 32;
+    f32x4 acc[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    fetch(0);
+    for (int k0 = 0; k0 < N; k0 += XSB_K) {
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if (k0 + XSB_K < N)
+            fetch(k0 + XSB_K);
+#pragma unroll
+        for (int kk = 0; kk < XSB_K; kk += 32) {
+            bf16x8 ah[RB], al[RB], bh[CB], bl[CB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int off = (wrow + 16 * i + li) * XSB_LD + kk + 8 * lg;
+                ah[i] = *reinterpret_cast<const bf16x8 *>(Ah + off);
+                al[i] = *reinterpret_cast<const bf16x8 *>(Al + off);
+            }
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                const int off = (wcol + 16 * j + li) * XSB_LD + kk + 8 * lg;
+                bh[j] = *reinterpret_cast<const bf16x8 *>(Bsh + off);
+                bl[j] = *reinterpret_cast<const bf16x8 *>(Bsl + off);
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < CB; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        const int n = n0 + wcol + 16 * j + li;
+        if (n >= N)
+            continue;
+        float wr = 1.0f, wi = 0.0f;
+        if (scale != nullptr) {
+            wr = scale[2 * n];
+            wi = scale[2 * n + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t s = s0 + wrow / 2 + 8 * i + XLayout<float>::sig(lg, h);
+                if (s >= batch)
+                    continue;
+                const float xr = acc[i][j][XLayout<float>::re(h)], xi = acc[i][j][XLayout<float>::im(h)];
+                float *dst = C + ((size_t)s * (size_t)N + (size_t)n) * 2;
                 dst[0] = xr * wr - xi * wi;
                 dst[1] = xr * wi + xi * wr;
             }

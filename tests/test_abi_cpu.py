@@ -147,7 +147,6 @@ def test_xft_host_nodes_and_vectors_match_oracle(lib, N):
 def test_xft_argument_errors(lib):
     h = ctypes.c_void_p()
     dp = ctypes.POINTER(ctypes.c_double)
-    assert lib.xft_plan_create(ctypes.byref(h), 64, 2) == _lib.LCT_ERR_UNSUPPORTED
     assert lib.xft_plan_create(ctypes.byref(h), 64, 7) == _lib.LCT_ERR_ARG
     assert lib.xft_plan_create(ctypes.byref(h), 0, 0) == _lib.LCT_ERR_UNSUPPORTED_N
     assert lib.xft_plan_create(ctypes.byref(h), 16385, 0) == _lib.LCT_ERR_UNSUPPORTED_N
@@ -159,7 +158,8 @@ def test_xft_argument_errors(lib):
     # workspace: N complex weights (rounded up to even) + batch x N complex
     assert lib.xft_workspace_size(100, 0, 3) == (100 + 300) * 8
     assert lib.xft_workspace_size(101, 1, 3) == (102 + 303) * 16
-    assert lib.xft_workspace_size(100, 2, 3) == 0
+    assert lib.xft_workspace_size(100, 2, 3) == (100 + 300) * 8
+    assert lib.xft_workspace_size(100, 5, 3) == 0
     lib.xft_plan_destroy(None)
 
 

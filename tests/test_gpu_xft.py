@@ -97,6 +97,23 @@ def test_xft_eigenvectors(dtype):
     assert rel_rows(y, ref).max() <= 4 * TOL[dtype]
 
 
+@pytest.mark.parametrize("N,batch", [(1, 3), (3, 5), (17, 70), (100, 64), (257, 9), (1000, 33), (4096, 40)])
+def test_xft_splitbf16_matches_oracle(N, batch):
+    """Split-BF16 products (x = hi + lo, three BF16 matrix-core products, FP32 accumulation):
+    the bound of the split-BF16 variant, 2e-4."""
+    print(f"[xft-sb] N={N} batch={batch}", flush=True)
+    x = dev(inputs(N, batch, 400 + N), torch.complex64)
+    fin = x.cpu().numpy().astype(np.complex128)
+    U = oracle.hermite_vectors(N)
+    key = (N, "sb")
+    if key not in _PLANS:
+        _PLANS[key] = lct.xft_plan_create(N, lct.LCT_FP32_SPLITBF16)
+    for z in [0.7 * np.exp(0.9j), -1.0, 0.3]:
+        y = lct.xft_exec(_PLANS[key], z, x).cpu().numpy().astype(np.complex128)
+        e = rel_rows(y, oracle.xft(fin, z, U))
+        assert e.max() <= 2e-4, (N, batch, z, e.max())
+
+
 def test_xft_in_place_and_errors():
     N, batch = 200, 7
     x = dev(inputs(N, batch, 5), torch.complex128)
