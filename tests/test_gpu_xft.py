@@ -131,3 +131,43 @@ def test_xft_in_place_and_errors():
         lct.xft_exec(p, 0.5, x.to(torch.complex64))
     empty = torch.empty(0, N, dtype=torch.complex128, device="cuda")
     assert lct.xft_exec(p, 0.5, empty).shape == (0, N)
+
+
+def test_graph_capture_replays_match_eager():
+    """xft_exec (weights kernel + two GEMM launches), the shared-order fractional
+    transform (spectrum launch + main launch) and a scaled-grid LCT plan enqueue
+    kernels only, with caller-owned workspaces: recorded into a HIP graph, every
+    replay (with unrelated eager work and synchronisations in between) matches
+    the eager result."""
+    N, B = 1024, 9
+    x = dev(inputs(N, B, 61), torch.complex64)
+    px = plan_of(N, torch.complex64)
+    wsx = torch.empty(lct.xft_workspace_size(N, lct.LCT_FP32, B), dtype=torch.uint8, device="cuda")
+    pf = lct.lct_plan_create(N, 1.0, 0.0, 0.0, 1.0, precision=lct.LCT_FP32)
+    wsf = torch.empty(lct.frft_workspace_size(N, lct.LCT_FP32, B), dtype=torch.uint8, device="cuda")
+    ps = lct.lct_plan_create(N, 0.7, 1.3, (0.7 * 0.4 - 1) / 1.3, 0.4, precision=lct.LCT_FP32, scale=1.6)
+    z = 0.8 * np.exp(-0.6j)
+    eager = [lct.xft_exec(px, z, x, ws=wsx).clone(), lct.frft_exec(pf, z, x, ws=wsf).clone(),
+             lct.lct_exec(ps, x).clone()]
+    outs = [torch.empty_like(x) for _ in range(3)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        lct.xft_exec(px, z, x, out=outs[0], ws=wsx)
+        lct.frft_exec(pf, z, x, out=outs[1], ws=wsf)
+        lct.lct_exec(ps, x, out=outs[2])
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        lct.xft_exec(px, z, x, out=outs[0], ws=wsx)
+        lct.frft_exec(pf, z, x, out=outs[1], ws=wsf)
+        lct.lct_exec(ps, x, out=outs[2])
+    for r in range(4):
+        for o in outs:
+            o.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), r
