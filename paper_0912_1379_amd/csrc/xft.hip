@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/lct.h"
@@ -29,6 +30,25 @@ struct xft_plan_s {
 namespace {
 
 constexpr int64_t XFT_MAX_N = 16384;
+
+// Runs body(lo, hi) over [0, n) split across up to 16 host threads (the
+// per-zero and per-vector work below is independent).
+template <typename F>
+void parallel_ranges(int64_t n, F body)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::min<int64_t>(std::max<unsigned>(hw, 1u), 16);
+    nt = std::min<int64_t>(nt, std::max<int64_t>(1, n / 4));
+    if (nt <= 1) {
+        body(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t i = 0; i < nt; ++i)
+        th.emplace_back(body, n * i / nt, n * (i + 1) / nt);
+    for (auto &t : th)
+        t.join();
+}
 
 // Eigenvalues of the symmetric tridiagonal matrix H of §2 (zero diagonal,
 // off-diagonal sqrt(i / 2), i = 1 .. N-1), i.e. the zeros of H_N, by the QL
@@ -52,14 +72,14 @@ void tridiag_zeros(int64_t N, std::vector<double> &d)
                 break;
             // Wilkinson shift from the leading 2 x 2 block at l
             double g = (d[(size_t)l + 1] - d[(size_t)l]) / (2.0 * e[(size_t)l]);
-            double r = hypot(g, 1.0);
+            double r = sqrt(g * g + 1.0);
             g = d[(size_t)m] - d[(size_t)l] + e[(size_t)l] / (g + (g >= 0 ? r : -r));
             double s = 1.0, c = 1.0, p = 0.0;
             int64_t i = m - 1;
             bool split = false;
             for (; i >= l; --i) {
                 const double f = s * e[(size_t)i], b = c * e[(size_t)i];
-                r = hypot(f, g);
+                r = sqrt(f * f + g * g); // entries are O(sqrt(N)): no overflow
                 e[(size_t)i + 1] = r;
                 if (r == 0.0) {
                     d[(size_t)i + 1] -= p;
@@ -98,7 +118,8 @@ void polish_zeros(int64_t N, std::vector<double> &x)
         a[(size_t)n] = sqrt(2.0 / (double)(n + 1));
         b[(size_t)n] = sqrt((double)n / (double)(n + 1));
     }
-    for (int64_t k = N / 2; k < N; ++k) {
+    parallel_ranges(N - N / 2, [&](int64_t lo, int64_t hi) {
+    for (int64_t k = N / 2 + lo; k < N / 2 + hi; ++k) {
         double xk = x[(size_t)k];
         for (int it = 0; it < 3; ++it) {
             double pm = 0.0, p = 1.0; // phi_{n-1}, phi_n up to a common factor
@@ -122,26 +143,31 @@ void polish_zeros(int64_t N, std::vector<double> &x)
         x[(size_t)k] = xk;
         x[(size_t)(N - 1 - k)] = -xk;
     }
+    });
     if (N % 2 == 1)
         x[(size_t)(N / 2)] = 0.0;
 }
 
-// U[n][k] = (u_k)_n of eq. (ortvec), 0-based:
+// Ut[k][n] = (u_k)_n of eq. (ortvec), 0-based (row k of Ut is column k of U):
 //   (u_k)_n = (-1)^(N+k+1) phi_n(x_k) / (sqrt(N) phi_{N-1}(x_k)),
 // the normalisation being the Christoffel-Darboux sum
-// sum_n phi_n(x_k)^2 = N phi_{N-1}(x_k)^2 at a zero of phi_N.  Each column
+// sum_n phi_n(x_k)^2 = N phi_{N-1}(x_k)^2 at a zero of phi_N.  Each vector
 // runs the recurrence once, keeping a running power-of-two exponent per n so
-// that no earlier value is rescaled.
-void ortho_vectors(int64_t N, const std::vector<double> &x, double *U)
+// that no earlier value is rescaled; values 2^-1200 below the last one and
+// smaller underflow to zero.
+void ortho_vectors_t(int64_t N, const std::vector<double> &x, double *Ut)
 {
-    std::vector<double> a((size_t)N), b((size_t)N), val((size_t)N);
-    std::vector<int> ex((size_t)N);
+    const double down[4] = {1.0, 0x1p-400, 0x1p-800, 0.0};
+    std::vector<double> a((size_t)N), b((size_t)N);
     for (int64_t n = 0; n < N; ++n) {
         a[(size_t)n] = sqrt(2.0 / (double)(n + 1));
         b[(size_t)n] = sqrt((double)n / (double)(n + 1));
     }
     const double rn = 1.0 / sqrt((double)N);
-    for (int64_t k = 0; k < N; ++k) {
+    parallel_ranges(N, [&](int64_t lo, int64_t hi) {
+    std::vector<double> val((size_t)N);
+    std::vector<int> ex((size_t)N);
+    for (int64_t k = lo; k < hi; ++k) {
         const double xk = x[(size_t)k];
         double pm = 0.0, p = 1.0;
         int e = 0;
@@ -163,9 +189,32 @@ void ortho_vectors(int64_t N, const std::vector<double> &x, double *U)
         const int elast = ex[(size_t)N - 1];
         const double sgn = ((N + k + 1) % 2 == 0) ? 1.0 : -1.0;
         const double scale = sgn * rn / last;
-        for (int64_t n = 0; n < N; ++n)
-            U[(size_t)n * (size_t)N + (size_t)k] = ldexp(val[(size_t)n], 400 * (ex[(size_t)n] - elast)) * scale;
+        double *row = Ut + (size_t)k * (size_t)N;
+        for (int64_t n = 0; n < N; ++n) {
+            const int d = elast - ex[(size_t)n]; // >= 0
+            row[n] = val[(size_t)n] * down[d < 3 ? d : 3] * scale;
+        }
     }
+    });
+}
+
+// dst = src^T for N x N row-major matrices: 32 x 32 tiles (a tile writes 32
+// rows, few enough pages for the TLB), bands of tile rows across threads.
+void transpose(int64_t N, const double *src, double *dst)
+{
+    constexpr int64_t TB = 32;
+    const int64_t nb = (N + TB - 1) / TB;
+    parallel_ranges(nb, [&](int64_t lo, int64_t hi) {
+        for (int64_t bi = lo; bi < hi; ++bi) {
+            const int64_t i0 = bi * TB, i1 = std::min(i0 + TB, N);
+            for (int64_t j0 = 0; j0 < N; j0 += TB) {
+                const int64_t j1 = std::min(j0 + TB, N);
+                for (int64_t i = i0; i < i1; ++i)
+                    for (int64_t j = j0; j < j1; ++j)
+                        dst[(size_t)j * (size_t)N + (size_t)i] = src[(size_t)i * (size_t)N + (size_t)j];
+            }
+        }
+    });
 }
 
 int host_nodes(int64_t N, std::vector<double> &x)
@@ -319,7 +368,9 @@ int xft_vectors(int64_t N, double *U)
     int rc = host_nodes(N, v);
     if (rc)
         return rc;
-    ortho_vectors(N, v, U);
+    std::vector<double> Ut((size_t)N * (size_t)N);
+    ortho_vectors_t(N, v, Ut.data());
+    transpose(N, Ut.data(), U);
     return LCT_OK;
 }
 
@@ -335,10 +386,8 @@ int xft_plan_create(xft_plan *out, int64_t N, lct_precision prec)
     if (rc)
         return rc;
     std::vector<double> U((size_t)N * (size_t)N), Ut((size_t)N * (size_t)N);
-    ortho_vectors(N, x, U.data());
-    for (int64_t n = 0; n < N; ++n)
-        for (int64_t k = 0; k < N; ++k)
-            Ut[(size_t)k * (size_t)N + (size_t)n] = U[(size_t)n * (size_t)N + (size_t)k];
+    ortho_vectors_t(N, x, Ut.data());
+    transpose(N, Ut.data(), U.data());
     xft_plan p = new (std::nothrow) xft_plan_s{N, (int)prec, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     if (!p)
         return LCT_ERR_ARG;
