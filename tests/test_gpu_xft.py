@@ -114,6 +114,39 @@ def test_xft_splitbf16_matches_oracle(N, batch):
         assert e.max() <= 2e-4, (N, batch, z, e.max())
 
 
+@pytest.mark.parametrize("prec,tol", [(lct.LCT_FP32, 2e-5), (lct.LCT_FP32_SPLITBF16, 2e-4)])
+def test_xft_large_eigenvectors(prec, tol):
+    """N = 8192: rows of U (the library's host computation, itself pinned against the
+    oracle at smaller N) are eigenvectors, F_z U[n] = sqrt(2 pi) z^n U[n]."""
+    N = 8192
+    print(f"[xft] N={N} prec={prec}", flush=True)
+    U = lct.xft_vectors(N)
+    rows = [0, 1, 2, 1000, 4095, 8191]
+    x = dev(U[rows].astype(np.complex128), torch.complex64)
+    z = np.exp(0.3j)  # |z| = 1: every eigenvalue has modulus sqrt(2 pi)
+    p = lct.xft_plan_create(N, prec)
+    y = lct.xft_exec(p, z, x).cpu().numpy().astype(np.complex128)
+    ref = np.stack([np.sqrt(2 * np.pi) * z ** n * U[n] for n in rows])
+    assert rel_rows(y, ref).max() <= tol
+    p.destroy()
+
+
+def test_xft_maximum_size_identities():
+    """N = 16384, the largest plan: F_1 = sqrt(2 pi) I and, since the zeros are symmetric
+    and phi_n has parity (-1)^n, F_{-1} f = sqrt(2 pi) f reversed."""
+    N, B = 16384, 3
+    print(f"[xft] N={N}", flush=True)
+    x = dev(inputs(N, B, 11), torch.complex64)
+    fin = x.cpu().numpy().astype(np.complex128)
+    p = lct.xft_plan_create(N, lct.LCT_FP32)
+    y1 = lct.xft_exec(p, 1.0, x).cpu().numpy().astype(np.complex128)
+    ym = lct.xft_exec(p, -1.0, x).cpu().numpy().astype(np.complex128)
+    s2 = np.sqrt(2 * np.pi)
+    assert rel_rows(y1, s2 * fin).max() <= 2e-5
+    assert rel_rows(ym, s2 * fin[:, ::-1]).max() <= 2e-5
+    p.destroy()
+
+
 def test_xft_in_place_and_errors():
     N, batch = 200, 7
     x = dev(inputs(N, batch, 5), torch.complex128)
