@@ -322,7 +322,7 @@ hipError_t xft_launch(const xft_plan_s *p, double zr, double zi, const void *in,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const int ncol = (N + XC - 1) / XC;
+    const int ncol = (N + XTile<R>::C - 1) / XTile<R>::C;
     const int64_t nsig = (batch + XS - 1) / XS;
     const int ntiles = (int)(nsig * ncol);
     const size_t lds = xft_lds_bytes((int)sizeof(R));

@@ -59,8 +59,9 @@ template <> struct XLayout<double> {
     static constexpr int im(int h) { return h + 2; }
 };
 
-// Work-group tile: XS signals (2 XS product rows) x XC columns, K in steps of
-// XK; 256 threads = 4 waves as 2 x 2, each wave XS rows x XC/2 columns.  The
+// Work-group tile: XS signals (2 XS product rows) x XC columns (k_xft_gemm:
+// XTile<R>::C), K in steps of XK; 256 threads = 4 waves as 2 x 2, each wave
+// XS rows x half the columns.  The
 // launch bound asks for two work-groups per CU (at most 256 registers per
 // lane): at one wave per SIMD the FP64 products stalled at every barrier.
 // Measured at 4096 x 4096 against this shape: K steps of 32, and two LDS
@@ -69,7 +70,17 @@ constexpr int XS = 64, XC = 128, XK = 16, XPAD = 1;
 constexpr int XTHREADS = 256;
 constexpr int XA_LD = XK + XPAD; // LDS row stride (elements)
 
-__host__ __device__ constexpr size_t xft_lds_bytes(int esize) { return (size_t)(2 * XS + XC) * XA_LD * esize; }
+// Columns per work-group of k_xft_gemm: 256 for FP32 (a wave's 64 x 128
+// outputs reuse each fragment read over more products), 128 for FP64 (whose
+// accumulators would not fit twice the width at two work-groups per CU).
+template <typename R> struct XTile {
+    static constexpr int C = sizeof(R) == 4 ? 256 : 128;
+};
+
+__host__ __device__ constexpr size_t xft_lds_bytes(int esize)
+{
+    return (size_t)(2 * XS + (esize == 4 ? 256 : 128)) * XA_LD * esize;
+}
 
 // C[s][n] = scale[n] * sum_k A[s][k] Bm[n][k]   (scale may be null: 1)
 // A: batch x K complex, Bm: Ncol x K real, C: batch x Ncol complex, all
@@ -81,28 +92,30 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm(const R *__restrict__ 
 {
     using acc_t = typename XMma<R>::acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int XCR = XTile<R>::C;
     R *As = reinterpret_cast<R *>(smem_raw); // [2 XS][XA_LD]
-    R *Bs = As + 2 * XS * XA_LD;             // [XC][XA_LD]
+    R *Bs = As + 2 * XS * XA_LD;             // [XCR][XA_LD]
 
     // signal-major logical tiles; each XCD takes a contiguous range, so the
     // work-groups that share a signal tile share one L2
     const int tile = xcd_remap((int)blockIdx.x, ntiles);
     const int st = tile / ncol_tiles, ct = tile - st * ncol_tiles;
     const int64_t s0 = (int64_t)st * XS;
-    const int n0 = ct * XC;
+    const int n0 = ct * XCR;
 
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int wrow = (wave >> 1) * XS;       // first product row of this wave (of 2 XS)
-    const int wcol = (wave & 1) * (XC / 2);  // first column of this wave (of XC)
+    const int wcol = (wave & 1) * (XCR / 2); // first column of this wave (of XCR)
 
     // global -> register staging: A as XS signals x 4 threads x AQ complex,
-    // B as XC columns x 2 threads x BQ reals
-    static_assert(XS * 4 == XTHREADS && XC * 2 == XTHREADS, "staging covers the tile");
-    constexpr int AQ = XK / 4, BQ = XK / 2;
+    // B as XCR columns x BT threads x BQ reals
+    constexpr int BT = XTHREADS / XCR;
+    static_assert(XS * 4 == XTHREADS && XCR * BT == XTHREADS, "staging covers the tile");
+    constexpr int AQ = XK / 4, BQ = XK / BT;
     const int as_ = tid >> 2, ak = (tid & 3) * AQ;
-    const int bn = tid >> 1, bk = (tid & 1) * BQ;
+    const int bn = tid / BT, bk = (tid % BT) * BQ;
     const bool a_live = s0 + as_ < batch;
     const bool b_live = n0 + bn < N;
     const R *arow = A + (size_t)(a_live ? s0 + as_ : 0) * 2 * (size_t)N;
@@ -136,7 +149,7 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm(const R *__restrict__ 
             Bs[bn * XA_LD + bk + q] = rb[q];
     };
 
-    constexpr int RB = XS / 16, CB = XC / 32; // 16 x 16 blocks per wave
+    constexpr int RB = XS / 16, CB = XCR / 32; // 16 x 16 blocks per wave
     acc_t acc[RB][CB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
