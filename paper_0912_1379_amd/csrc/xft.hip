@@ -295,7 +295,7 @@ hipError_t xft_launch_sb(const xft_plan_s *p, double zr, double zi, const void *
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    const int ncol = (N + XC - 1) / XC;
+    const int ncol = (N + XSB_C - 1) / XSB_C;
     const int ntiles = (int)((batch + XS - 1) / XS * ncol);
     const size_t lds = xft_sb_lds_bytes();
     if ((e = allow_lds((const void *)k_xft_gemm_sb, lds)) != hipSuccess)

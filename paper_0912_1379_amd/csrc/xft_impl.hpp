@@ -220,10 +220,15 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm(const R *__restrict__ 
 // while staged into LDS; U is split once, at plan creation (Bh, Bl, rows
 // padded to ldb, a multiple of 8, with zeros, so that they load 16 bytes at
 // a time).
-constexpr int XSB_K = 64;             // K step (two MFMA K blocks of 32)
-constexpr int XSB_LD = XSB_K + 8;     // LDS row stride in bf16 (144 bytes)
+// Work-group tile: 64 signals x 256 columns, each wave 64 x 128 outputs as
+// 4 x 8 blocks (each fragment read feeds 3 x 4 or 3 x 8 products); K in
+// steps of one MFMA K block, which keeps the hi and lo tiles of A and B in
+// 60 KiB of LDS, two work-groups per CU.
+constexpr int XSB_C = 256;            // columns per work-group
+constexpr int XSB_K = 32;             // K step
+constexpr int XSB_LD = XSB_K + 8;     // LDS row stride in bf16 (80 bytes)
 
-__host__ __device__ constexpr size_t xft_sb_lds_bytes() { return (size_t)2 * (2 * XS + XC) * XSB_LD * 2; }
+__host__ __device__ constexpr size_t xft_sb_lds_bytes() { return (size_t)2 * (2 * XS + XSB_C) * XSB_LD * 2; }
 
 __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__restrict__ A,
                                                             const __bf16 *__restrict__ Bh,
@@ -234,25 +239,28 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__rest
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __bf16 *Ah = reinterpret_cast<__bf16 *>(smem_raw); // [2 XS][XSB_LD]
     __bf16 *Al = Ah + 2 * XS * XSB_LD;
-    __bf16 *Bsh = Al + 2 * XS * XSB_LD; // [XC][XSB_LD]
-    __bf16 *Bsl = Bsh + XC * XSB_LD;
+    __bf16 *Bsh = Al + 2 * XS * XSB_LD; // [XSB_C][XSB_LD]
+    __bf16 *Bsl = Bsh + XSB_C * XSB_LD;
 
     const int tile = xcd_remap((int)blockIdx.x, ntiles);
     const int st = tile / ncol_tiles, ct = tile - st * ncol_tiles;
     const int64_t s0 = (int64_t)st * XS;
-    const int n0 = ct * XC;
+    const int n0 = ct * XSB_C;
 
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int wrow = (wave >> 1) * XS;
-    const int wcol = (wave & 1) * (XC / 2);
+    const int wcol = (wave & 1) * (XSB_C / 2);
 
-    // staging: A as XS signals x 4 threads x 16 complex; B as XC columns x
-    // 2 threads x 32 values of each of Bh, Bl
-    constexpr int AQ = XSB_K / 4, BQ = XSB_K / 2;
+    // staging: A as XS signals x 4 threads x AQ complex; B as XSB_C columns
+    // x BT threads x BQ values of each of Bh, Bl
+    constexpr int BT = XTHREADS / XSB_C;
+    static_assert(XS * 4 == XTHREADS && XSB_C * BT == XTHREADS, "staging covers the tile");
+    constexpr int AQ = XSB_K / 4, BQ = XSB_K / BT;
+    static_assert(AQ % 8 == 0 && BQ % 8 == 0, "16-byte chunks");
     const int as_ = tid >> 2, ak = (tid & 3) * AQ;
-    const int bn = tid >> 1, bk = (tid & 1) * BQ;
+    const int bn = tid / BT, bk = (tid % BT) * BQ;
     const bool a_live = s0 + as_ < batch;
     const bool b_live = n0 + bn < N;
     const float *arow = A + (size_t)(a_live ? s0 + as_ : 0) * 2 * (size_t)N;
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__rest
         }
     };
 
-    constexpr int RB = XS / 16, CB = XC / 32;
+    constexpr int RB = XS / 16, CB = XSB_C / 32;
     f32x4 acc[RB][CB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__rest
             fetch(k0 + XSB_K);
 #pragma unroll
         for (int kk = 0; kk < XSB_K; kk += 32) {
-            bf16x8 ah[RB], al[RB], bh[CB], bl[CB];
+            bf16x8 ah[RB], al[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int off = (wrow + 16 * i + li) * XSB_LD + kk + 8 * lg;
@@ -332,17 +340,15 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__rest
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int off = (wcol + 16 * j + li) * XSB_LD + kk + 8 * lg;
-                bh[j] = *reinterpret_cast<const bf16x8 *>(Bsh + off);
-                bl[j] = *reinterpret_cast<const bf16x8 *>(Bsl + off);
-            }
+                const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(Bsh + off);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Bsl + off);
 #pragma unroll
-            for (int i = 0; i < RB; ++i)
-#pragma unroll
-                for (int j = 0; j < CB; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                for (int i = 0; i < RB; ++i) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
                 }
+            }
         }
     }
 
