@@ -19,6 +19,11 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             samples on s x_k (outputs on 4 b x_j / (pi s));
                             pinned by the Gaussian closed form on scaled grids
                             and by chains of two transforms.
+``lct_same_grid(f, a, b, d)`` LCT of §1 for complex a, b, d as a Riemann sum
+                            with output on the input grid; pinned by the
+                            fractional transform (a = d), O1 at b = pi/4 for
+                            real matrices, the complex Gaussian closed form
+                            and mpmath brute force.
 ``lct_adjoint``             conjugate transpose of the same matrix; pinned by
                             the inner-product identity and unitarity.
 ``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d);
@@ -70,6 +75,8 @@ def _load():
     lib.oracle_lct_rows.restype = ctypes.c_int
     lib.oracle_lct_rows_scaled.argtypes = [i64, d, d, d, d, d, _dp, _i64p, i64, _dp]
     lib.oracle_lct_rows_scaled.restype = ctypes.c_int
+    lib.oracle_lct_same_rows.argtypes = [i64, d, d, d, d, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_lct_same_rows.restype = ctypes.c_int
     lib.oracle_lct_adjoint.argtypes = [i64, d, d, d, d, _dp, _dp]
     lib.oracle_lct_adjoint.restype = ctypes.c_int
     lib.oracle_lct_param_grad.argtypes = [i64, d, d, d, d, _dp, _dp, _dp]
@@ -136,6 +143,26 @@ def lct(f, a: float, b: float, c: float, d: float, rows=None, scale: float = 1.0
                                         _ptr(out.view(np.float64)))
     if rc != 0:
         raise ValueError(f"oracle_lct_rows failed ({rc})")
+    return out
+
+
+def lct_same_grid(f, a: complex, b: complex, d: complex, rows=None) -> np.ndarray:
+    """LCT of §1 for a complex matrix, output on the input grid (O4); 1-D f."""
+    f = _cplx_in(f)
+    N = f.shape[0]
+    if rows is None:
+        r = None
+        nr = N
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = r.shape[0]
+    a, b, d = complex(a), complex(b), complex(d)
+    out = np.empty(nr, dtype=np.complex128)
+    rc = _load().oracle_lct_same_rows(N, a.real, a.imag, b.real, b.imag, d.real, d.imag, _ptr(f.view(np.float64)),
+                                      None if r is None else r.ctypes.data_as(_i64p), nr,
+                                      _ptr(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError(f"oracle_lct_same_rows failed ({rc})")
     return out
 
 

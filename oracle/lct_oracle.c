@@ -167,6 +167,52 @@ int oracle_lct_rows(int64_t N, double a, double b, double c, double d,
 }
 
 /*
+ * O4: the LCT of §1 for a complex matrix (a, b, d complex, b != 0; c is
+ * implied by ad - bc = 1 and does not enter) as the Riemann sum of its
+ * integral on one grid for input and output, y_j = x_j (eq. asymcer):
+ *   G_j = sum_k h (2 pi i b)^(-1/2) exp(i [a x_k^2 - 2 x_k x_j + d x_j^2]/(2b)) f_k,
+ * the principal branch of the root.  For a = d = (z + 1/z)/2, b = i (z - 1/z)/2
+ * this is the same-grid fractional transform of eqs. (fasy)-(cuadtrfor) up to
+ * the factor sqrt(2 pi / z).  rows == NULL means every row (nrows must be N).
+ * Returns 0, or -1 on bad arguments.
+ * Pinned: the fractional transform for a = d, the chirp-DFT-chirp sum O1 for
+ * real matrices with b = pi/4 (where the two grids coincide), the complex
+ * Gaussian closed form, mpmath brute force.
+ */
+int oracle_lct_same_rows(int64_t N, double ar, double ai, double br, double bi, double dr, double di,
+                         const double *f, const int64_t *rows, int64_t nrows, double *out)
+{
+    if (N < 1 || f == NULL || out == NULL || nrows < 0 || (br == 0.0 && bi == 0.0))
+        return -1;
+    if (rows == NULL && nrows != N)
+        return -1;
+    const long double h = PI_L / sqrtl(2.0L * (long double)N);
+    const long double complex A = CMPLXL(ar, ai), B = CMPLXL(br, bi), D = CMPLXL(dr, di);
+    const long double complex w = CMPLXL(0.0L, 1.0L) / (2.0L * B); /* i / (2b) */
+    const long double complex amp = h / csqrtl(CMPLXL(0.0L, 2.0L * PI_L) * B);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t j = rows ? rows[r] : r;
+        if (j < 0 || j >= N) {
+            bad = 1;
+            continue;
+        }
+        const long double xj = node_l(N, j);
+        long double complex acc = 0;
+        for (int64_t k = 0; k < N; ++k) {
+            const long double xk = node_l(N, k);
+            const long double complex e = w * (A * xk * xk - 2.0L * xk * xj + D * xj * xj);
+            acc += cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+        }
+        const long double complex v = amp * acc;
+        out[2 * r] = (double)creall(v);
+        out[2 * r + 1] = (double)cimagl(v);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * Adjoint of the discrete LCT matrix of oracle_lct_rows (b != 0):
  *   (L^H g)_k = sum_j conj(L_jk) g_j.
  * This is the gradient of a real loss with respect to the input samples in

@@ -356,3 +356,62 @@ def test_nodes_spacing_and_symmetry():
         assert np.allclose(x, -x[::-1], atol=1e-15 * max(1, N))
         if N > 1:
             assert np.allclose(np.diff(x), np.pi / np.sqrt(2 * N), rtol=1e-13)
+
+
+# --- same-grid LCT for complex matrices (O4) -----------------------------------
+@pytest.mark.parametrize("z", [0.6 * np.exp(-1.1j), -0.7 + 0.2j, 0.9 * np.exp(2.5j), 0.5, 0.3j])
+def test_same_grid_equal_corners_is_the_fractional_transform(z):
+    """a = d = (z + 1/z)/2, b = i (z - 1/z)/2 turns the LCT kernel into the fractional kernel
+    of eq. (fasy) times (2 pi / z)^(-1/2): against the separately pinned fractional oracle."""
+    N = 200
+    x = oracle.nodes(N)
+    f = np.exp(-(x - 0.3) ** 2 / 1.2 + 0.2j * x * x)
+    a = d = (z + 1 / z) / 2
+    b = 1j * (z - 1 / z) / 2
+    g = oracle.lct_same_grid(f, a, b, d) * np.sqrt(2 * np.pi / z)
+    assert relerr(g, oracle.frft(f, z)) < 1e-13
+
+
+@pytest.mark.parametrize("a,d", [(0.7, 1.3), (-1.4, 0.2), (1.9, -0.6)])
+def test_same_grid_is_O1_where_the_grids_coincide(a, d):
+    """For a real matrix with b = pi/4 the Algorithm's output nodes 4 b x_j / pi are the input
+    nodes, so the same-grid sum and O1 are the same Riemann sum."""
+    N = 300
+    b = np.pi / 4
+    g = np.random.default_rng(3)
+    f = g.standard_normal(N) + 1j * g.standard_normal(N)
+    ref = oracle.lct(f, a, b, (a * d - 1) / b, d)
+    assert relerr(oracle.lct_same_grid(f, a, b, d), ref) < 1e-12
+
+
+@pytest.mark.parametrize("M", [(0.5 + 0.3j, 1.0 + 0.2j, 0.8 + 0.4j), (1.2 + 0.5j, 0.7 + 0.1j, 0.3 + 0.6j),
+                               (-0.4 - 0.3j, -0.9 + 0.3j, -0.5 - 0.4j), (0.9 + 0.1j, 0.6 - 0.2j, 1.1 + 0.05j)])
+def test_same_grid_complex_gaussian_closed_form(M):
+    """Complex (damped) matrices: the sum reproduces the Gaussian integral of the LCT with complex
+    parameters on the grid y_j = x_j (the kernel times the Gaussian input decays in x and y for
+    these matrices; the last three also split into bounded Toeplitz or Hankel factors)."""
+    a, b, d = M
+    N = 512
+    x = oracle.nodes(N)
+    al, be, ga = 0.5 + 0.3j, 0.4 - 0.2j, 0.1
+    G = oracle.lct_same_grid(np.exp(-(al * x * x + 2 * be * x + ga)), a, b, d)
+    assert relerr(G, gaussian_lct(x, al, be, ga, a, b, d)) < 1e-12
+
+
+def test_same_grid_mpmath_brute_force():
+    N = 7
+    a, b, d = 0.4 + 0.2j, -0.9 + 0.3j, -0.2 + 0.5j
+    g = np.random.default_rng(7)
+    f = g.standard_normal(N) + 1j * g.standard_normal(N)
+    G = oracle.lct_same_grid(f, a, b, d)
+    with mp.workdps(40):
+        A, B, D = mp.mpc(a.real, a.imag), mp.mpc(b.real, b.imag), mp.mpc(d.real, d.imag)
+        xs = [(2 * k - N + 1) * mp.pi / (2 * mp.sqrt(2 * N)) for k in range(N)]
+        amp = (mp.pi / mp.sqrt(2 * N)) / mp.sqrt(2j * mp.pi * B)
+        for j in range(N):
+            acc = mp.mpc(0)
+            for k in range(N):
+                acc += mp.exp(1j * (A * xs[k] ** 2 - 2 * xs[k] * xs[j] + D * xs[j] ** 2) / (2 * B)) * \
+                    mp.mpc(f[k].real, f[k].imag)
+            ref = complex(amp * acc)
+            assert abs(G[j] - ref) <= 1e-14 * max(1.0, abs(ref))
