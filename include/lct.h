@@ -184,6 +184,27 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
                       int64_t batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * LCT of §1 for a complex matrix (a, b, d complex, b != 0; c follows from
+ * ad - bc = 1 and does not enter), e.g. damped LCTs, with the output on the
+ * input grid (y_j = x_j, eq. asymcer), as the Riemann sum of the integral:
+ *   out[j] = h (2 pi i b)^(-1/2) sum_k exp(i [a x_k^2 - 2 x_k x_j + d x_j^2]/(2b)) in[k]
+ * (principal root).  For a = d = (z + 1/z)/2, b = i (z - 1/z)/2 this is
+ * frft_exec's transform divided by sqrt(2 pi / z).  Computed exactly (up to
+ * rounding) as chirp * Gaussian-chirp convolution * chirp in the Toeplitz
+ * form, or, input reversed, the Hankel form, whichever has all three factors
+ * of modulus <= 1; a matrix for which neither does (the sum would add and
+ * cancel exponentially large terms) gives LCT_ERR_DOMAIN.  Real matrices
+ * always qualify (unit-modulus chirps).  One matrix per call: its
+ * convolution kernel's spectrum is shared by the batch when a single-pass
+ * workspace is given.  Workspace, alignment and in != out as frft_exec_ws
+ * (frft_workspace_size).  b == 0 and LCT_FP32_SPLITBF16 give
+ * LCT_ERR_UNSUPPORTED.
+ */
+int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im,
+                       double d_re, double d_im, const void *in, void *out, int64_t batch, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/*
  * Ragged batch in one persistent launch: signals of different lengths, each
  * an LCT with its own matrix or a same-grid fractional transform with its own
  * order.  This extends the paper's single-transform statement to a batch.

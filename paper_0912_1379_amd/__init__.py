@@ -42,7 +42,7 @@ from ._lib import (LCT_ERR_ARG, LCT_ERR_DOMAIN, LCT_ERR_HIP, LCT_ERR_NOT_UNIMODU
 __all__ = [
     "Plan", "lct_plan_create", "lct_plan_create_ex", "lct_plan_create_scaled", "lct_plan_destroy", "lct_exec", "lct_exec_many",
     "lct_exec_adjoint", "lct_exec_many_adjoint", "lct_param_grad_many", "frft_exec", "frft_exec_many",
-    "frft_workspace_size", "RaggedPlan", "make_descriptors", "lct_ragged_plan_create", "lct_exec_ragged",
+    "frft_workspace_size", "lct_same_grid_exec", "RaggedPlan", "make_descriptors", "lct_ragged_plan_create", "lct_exec_ragged",
     "LCT_KIND_LCT", "LCT_KIND_FRFT",
     "lct_autotune", "lct_tune_candidates", "lct_tune_get", "lct_tune_set", "lct_tune_load", "lct_tune_save",
     "lct_tune_clear", "LCT_TUNE_LCT", "LCT_TUNE_FRFT",
@@ -421,6 +421,25 @@ def lct_nodes(N: int, b: float, d: float = 1.0, scale: float = 1.0):
                                           y.ctypes.data_as(dp))
         _lib.check(rc, "lct_nodes_scaled")
     return x, y
+
+
+def lct_same_grid_exec(x: torch.Tensor, a: complex, b: complex, d: complex, out=None, stream=None,
+                       ws=None) -> torch.Tensor:
+    """LCT of a complex matrix (a, b, d) with the output on the input grid (the
+    nodes of lct_nodes(N, ...)[0]); one matrix for every signal of x."""
+    _check_data(x, "x")
+    prec = _prec_of(x)
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    out = _out_like(x, out)
+    a, b, d = complex(a), complex(b), complex(d)
+    if ws is None:
+        ws = _workspace(frft_workspace_size(N, prec, batch), x.device)
+    rc = _lib.load().lct_same_grid_exec(N, prec, a.real, a.imag, b.real, b.imag, d.real, d.imag, x.data_ptr(),
+                                        out.data_ptr(), batch, 0 if ws is None else ws.data_ptr(),
+                                        0 if ws is None else ws.numel(), _stream_handle(stream))
+    _lib.check(rc, "lct_same_grid_exec")
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl3(const typ
         const int j = n20 + sl2 + L2 * n1;
         if (j < N) {
             C<R> y = cconj(l2[lds_pad(n1)]);
-            y = cmul(y, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
+            y = cmul(y, gauss_chirp<R>(k.omag, k.oph_hi, k.oph_lo, nsq(j, N)));
             y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
             stc<R>(out + (size_t)s * N + j, y);
         }

@@ -415,7 +415,7 @@ __global__ __launch_bounds__(LB) void k_frft(
         for (int e = 0; e < E / 2; ++e) {
             const int j = t + T * e;
             C<R> y = cconj(v[e]);
-            y = cmul(y, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
+            y = cmul(y, gauss_chirp<R>(k.omag, k.oph_hi, k.oph_lo, nsq(j, N)));
             y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
             stc<R>(dst + j, y);
         }

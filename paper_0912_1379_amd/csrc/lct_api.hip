@@ -123,6 +123,67 @@ size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
     return (size_t)batch * 2 * (size_t)(2 * N) * (fp64 ? 16 : 8);
 }
 
+// Constants of the same-grid LCT of a complex matrix (a, b, d; b != 0): the
+// Riemann sum of the integral of §1 with y_j = x_j,
+//   G_j = h (2 pi i b)^(-1/2) sum_k exp(w [a x_k^2 - 2 x_k x_j + d x_j^2]) f_k,  w = i / (2b),
+// split exactly with -2 x_k x_j = (x_j - x_k)^2 - x_j^2 - x_k^2 (Toeplitz:
+// input factor w (a - 1), kernel w, output factor w (d - 1)) or
+// -2 x_k x_j = -(x_j + x_k)^2 + x_j^2 + x_k^2 (Hankel, the input reversed so
+// that x_j + x_k = x_j - x_k': input factor w (a + 1), kernel -w, output
+// factor w (d + 1)).  The form whose three factors all have non-positive
+// real parts (every factor of modulus <= 1) is taken, Toeplitz first;
+// neither gives LCT_ERR_DOMAIN.
+int same_grid_const(int64_t N, double ar, double ai, double br, double bi, double dr, double di, FrConst *k)
+{
+    double wr, wi; // i / (2b)
+    cdiv(0.0, 1.0, 2.0 * br, 2.0 * bi, wr, wi);
+    auto mulw = [&](double xr, double xi, double &pr, double &pi_) {
+        pr = wr * xr - wi * xi;
+        pi_ = wr * xi + wi * xr;
+    };
+    auto bounded = [](double re, double im) { return re <= 1e-12 * fmax(1.0, fabs(im)); };
+    double tir, tii, tor, toi, hir, hii, hor, hoi;
+    mulw(ar - 1.0, ai, tir, tii);
+    mulw(dr - 1.0, di, tor, toi);
+    mulw(ar + 1.0, ai, hir, hii);
+    mulw(dr + 1.0, di, hor, hoi);
+    const bool toep = bounded(tir, tii) && bounded(wr, wi) && bounded(tor, toi);
+    const bool hank = bounded(hir, hii) && bounded(-wr, -wi) && bounded(hor, hoi);
+    if (!toep && !hank)
+        return LCT_ERR_DOMAIN;
+    *k = FrConst{};
+    k->special = 0;
+    k->hankel = toep ? 0 : 1;
+    const double inr = toep ? tir : hir, ini = toep ? tii : hii;
+    const double our = toep ? tor : hor, oui = toep ? toi : hoi;
+    const double kr = toep ? wr : -wr, ki = toep ? wi : -wi;
+    const double n = (double)N;
+    const DD pi{PI_HI, PI_LO};
+    // x^2 = pi^2 n^2 / (8N): log-modulus Re(.) pi^2 / (8N), turns Im(.) pi / (16N) per n^2
+    k->dmag = inr * PI_HI * PI_HI / (8.0 * n);
+    DD t = dd_div_d(dd_mul_d(pi, ini), 16.0 * n);
+    k->dph_hi = t.hi;
+    k->dph_lo = t.lo;
+    k->omag = our * PI_HI * PI_HI / (8.0 * n);
+    t = dd_div_d(dd_mul_d(pi, oui), 16.0 * n);
+    k->oph_hi = t.hi;
+    k->oph_lo = t.lo;
+    // h^2 m^2 = pi^2 m^2 / (2N): log-modulus Re pi^2 / (2N), turns Im pi / (4N) per m^2
+    k->kmag = kr * PI_HI * PI_HI / (2.0 * n);
+    t = dd_div_d(dd_mul_d(pi, ki), 4.0 * n);
+    k->kph_hi = t.hi;
+    k->kph_lo = t.lo;
+    // h (2 pi i b)^(-1/2) / (2N), principal root; 2 pi i b = -2 pi b_im + i 2 pi b_re
+    double sr, si;
+    csqrt_principal(-2.0 * PI_HI * bi, 2.0 * PI_HI * br, sr, si);
+    double qr, qi;
+    cdiv(1.0, 0.0, sr, si, qr, qi);
+    const double h = PI_HI / sqrt(2.0 * n);
+    k->cre = h * qr / (2.0 * n);
+    k->cim = h * qi / (2.0 * n);
+    return LCT_OK;
+}
+
 int frft_run(int64_t N, bool fp64, const double *Z2, const FrConst *k, const void *in, void *out, int64_t batch,
              void *ws, size_t ws_bytes, hipStream_t s)
 {
@@ -449,6 +510,28 @@ int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out
         return LCT_ERR_DOMAIN;
     FrConst k = fr_const(p->N, z_re, z_im);
     return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, ws_bytes, stream);
+}
+
+int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im,
+                       double d_re, double d_im, const void *in, void *out, int64_t batch, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
+{
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
+    if (prec != LCT_FP32 && prec != LCT_FP64)
+        return LCT_ERR_ARG;
+    for (double v : {a_re, a_im, b_re, b_im, d_re, d_im})
+        if (!isfinite(v))
+            return LCT_ERR_ARG;
+    if (b_re == 0.0 && b_im == 0.0)
+        return LCT_ERR_UNSUPPORTED; // b = 0 samples f at d y_j, off the grid
+    if (!smooth235(N))
+        return LCT_ERR_UNSUPPORTED_N;
+    FrConst k;
+    const int rc = same_grid_const(N, a_re, a_im, b_re, b_im, d_re, d_im, &k);
+    if (rc)
+        return rc;
+    return frft_run(N, prec == LCT_FP64, nullptr, &k, in, out, batch, ws, ws_bytes, stream);
 }
 
 size_t frft_workspace_size(int64_t N, lct_precision prec, int64_t batch)

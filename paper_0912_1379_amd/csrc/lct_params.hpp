@@ -203,12 +203,19 @@ __host__ __device__ inline LctConst lct_const_from(const NConst &nc, double a, d
 //   kmag/kph: log-modulus and turns of exp(-beta h^2 m^2) per m^2 (h^2 = pi^2/(2N))
 //   cre/cim:  h sqrt(2/(1-z^2)) / L, L = 2N the convolution length
 // special: 0 general, 1 for z = 1, 2 for z = -1 (continuum limits).
+// Same-grid convolution form  out_j = C e^{o x_j^2} sum_k e^{kappa h^2 (j-k)^2} e^{d x_k^2} in'_k
+// (in' = in, or in reversed for the Hankel form): log-modulus per n^2 and
+// phase in turns per n^2 (double-double) of the input factor d and the output
+// factor o (n = 2k - N + 1, x^2 = pi^2 n^2 / (8N)), and of the kernel per m^2;
+// C includes the 1 / (2N) of the inverse DFT.  The fractional transform has
+// o = d.
 struct FrConst {
     double dmag, dph_hi, dph_lo;
     double kmag, kph_hi, kph_lo;
     double cre, cim;
     int hankel;
     int special;
+    double omag, oph_hi, oph_lo;
 };
 
 __host__ __device__ inline void cdiv(double ar, double ai, double br, double bi, double &qr, double &qi)
@@ -279,6 +286,9 @@ __host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
     double h = PI_HI / sqrt(2.0 * n);
     k.cre = h * sr / (2.0 * n);
     k.cim = h * si / (2.0 * n);
+    k.omag = k.dmag;
+    k.oph_hi = k.dph_hi;
+    k.oph_lo = k.dph_lo;
     return k;
 }
 

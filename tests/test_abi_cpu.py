@@ -163,6 +163,21 @@ def test_xft_argument_errors(lib):
     lib.xft_plan_destroy(None)
 
 
+def test_same_grid_argument_errors(lib):
+    """Host-side validation of lct_same_grid_exec (nothing is launched)."""
+    f = lib.lct_same_grid_exec
+    ok = (0.9, 0.1, 0.6, -0.2, 1.1, 0.05)  # Toeplitz factors bounded
+    assert f(64, 0, 0.5, -0.3, 1.0, 0.2, 0.8, 0.4, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_DOMAIN  # neither form
+    assert f(64, 0, 0.4, 0.2, -0.9, 0.3, -0.2, 0.5, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_DOMAIN
+    assert f(64, 0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_UNSUPPORTED  # b = 0
+    assert f(64, 2, *ok, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_UNSUPPORTED
+    assert f(64, 5, *ok, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_ARG
+    assert f(7, 0, *ok, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert f(64, 0, float("nan"), 0.0, 1.0, 0.0, 1.0, 0.0, 8, 16, 1, None, 0, None) == _lib.LCT_ERR_ARG
+    assert f(64, 0, *ok, 8, 16, 0, None, 0, None) == _lib.LCT_OK  # empty batch
+    assert f(64, 0, *ok, 16, 16, 1, None, 0, None) == _lib.LCT_ERR_ARG  # in == out
+
+
 # --- autotuner table (host functions only) ------------------------------------
 def _cands(lib, N, prec, kind):
     n = ctypes.c_int(0)
