@@ -473,7 +473,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--signals", type=int, default=4096)
     ap.add_argument("--N", type=int, default=4096)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
