@@ -374,12 +374,39 @@ __device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
     }
 }
 
+// What one LDS exchange moves: PART < 0 whole complex values (a C<R> array),
+// PART = 0 / 1 only the real / imaginary parts (an R array, same indices).
+template <int PART, typename R> struct LdsElem {
+    using T = R;
+};
+template <typename R> struct LdsElem<-1, R> {
+    using T = C<R>;
+};
+template <int PART, typename R> __device__ __forceinline__ typename LdsElem<PART, R>::T part_of(const C<R> &a)
+{
+    if constexpr (PART == 0)
+        return a.x;
+    else if constexpr (PART == 1)
+        return a.y;
+    else
+        return a;
+}
+template <int PART, typename R> __device__ __forceinline__ void set_part(C<R> &a, const typename LdsElem<PART, R>::T &x)
+{
+    if constexpr (PART == 0)
+        a.x = x;
+    else if constexpr (PART == 1)
+        a.y = x;
+    else
+        a = x;
+}
+
 // Writes the outputs of a stage to their Stockham positions in LDS.
 // The padded index of p + s*d is lds_pad(p) + s*(d + d/16) when d is a
 // multiple of 16, and lds_pad(p) + s*d when all of p + s*d stay inside one
 // 16-element block; both keep one address per butterfly and constant offsets.
-template <int E, int RAD, typename R>
-__device__ __forceinline__ void stage_write(C<R> *lds, const C<R> *v, int t, int T, int Ns)
+template <int E, int RAD, int PART = -1, typename R>
+__device__ __forceinline__ void stage_write(typename LdsElem<PART, R>::T *lds, const C<R> *v, int t, int T, int Ns)
 {
     constexpr int Q = E / RAD;
 #pragma unroll
@@ -387,37 +414,37 @@ __device__ __forceinline__ void stage_write(C<R> *lds, const C<R> *v, int t, int
         int b = t + T * i;
         int j = b % Ns;
         int base = (b - j) * RAD + j;
-        C<R> *p = lds + lds_pad(base);
+        auto *p = lds + lds_pad(base);
         if ((Ns & 15) == 0) {
             const int st = Ns + (Ns >> 4);
 #pragma unroll
             for (int s = 0; s < RAD; ++s)
-                p[s * st] = v[i + Q * s];
+                p[s * st] = part_of<PART>(v[i + Q * s]);
         } else if ((base & 15) + (RAD - 1) * Ns < 16) {
 #pragma unroll
             for (int s = 0; s < RAD; ++s)
-                p[s * Ns] = v[i + Q * s];
+                p[s * Ns] = part_of<PART>(v[i + Q * s]);
         } else {
 #pragma unroll
             for (int s = 0; s < RAD; ++s)
-                lds[lds_pad(base + s * Ns)] = v[i + Q * s];
+                lds[lds_pad(base + s * Ns)] = part_of<PART>(v[i + Q * s]);
         }
     }
 }
 
-template <int E, typename R>
-__device__ __forceinline__ void stage_read(const C<R> *lds, C<R> *v, int t, int T)
+template <int E, int PART = -1, typename R>
+__device__ __forceinline__ void stage_read(const typename LdsElem<PART, R>::T *lds, C<R> *v, int t, int T)
 {
     if ((T & 15) == 0) {
-        const C<R> *p = lds + lds_pad(t);
+        const auto *p = lds + lds_pad(t);
         const int st = T + (T >> 4);
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            v[e] = p[e * st];
+            set_part<PART>(v[e], p[e * st]);
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e)
-            v[e] = lds[lds_pad(t + T * e)];
+            set_part<PART>(v[e], lds[lds_pad(t + T * e)]);
     }
 }
 
@@ -548,6 +575,38 @@ template <int E, int N, typename R>
 __device__ __forceinline__ void fft_lds_fixed(C<R> *v, C<R> *lds, int t)
 {
     fft_lds_fixed_from<E, N, 0, 1>(v, lds, t);
+}
+
+// Same transform with each exchange made in two halves, the real parts and
+// then the imaginary parts, through a buffer of lds_elems(N) R (half the LDS
+// of the whole-value exchange, for two more barriers per stage).
+template <int E, int N, int S, int NS, typename R>
+__device__ __forceinline__ void fft_lds_fixed_half_from(C<R> *v, R *lds, int t)
+{
+    constexpr int NST = fixed_nstages(N, E);
+    if constexpr (S < NST) {
+        constexpr int RAD = fixed_radix(N, E, S);
+        constexpr int T = N / E;
+        stage_compute<E, RAD>(v, t, T, NS);
+        if constexpr (S + 1 < NST) {
+            // reading the real parts leaves the imaginary parts of the stage's
+            // outputs in place for the second half
+            __syncthreads();
+            stage_write<E, RAD, 0>(lds, v, t, T, NS);
+            __syncthreads();
+            stage_read<E, 0>(lds, v, t, T);
+            __syncthreads();
+            stage_write<E, RAD, 1>(lds, v, t, T, NS);
+            __syncthreads();
+            stage_read<E, 1>(lds, v, t, T);
+        }
+        fft_lds_fixed_half_from<E, N, S + 1, NS * RAD>(v, lds, t);
+    }
+}
+template <int E, int N, typename R>
+__device__ __forceinline__ void fft_lds_fixed_half(C<R> *v, R *lds, int t)
+{
+    fft_lds_fixed_half_from<E, N, 0, 1>(v, lds, t);
 }
 
 template <int E, typename R>

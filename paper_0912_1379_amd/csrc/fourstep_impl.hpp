@@ -61,15 +61,15 @@ __global__ __launch_bounds__(LB) void k_fs1(
     const LctConst k = args.M4 != nullptr ? lct_const_from(args.nc, m4[0], m4[1], m4[2], m4[3]) : args.k;
     const R mag = (R)k.amp_mag;
     {
-        const ThreadChirp c = MODE == MODE_FWD
-                                  ? seq_chirp(k.pre_hi, k.pre_lo, true, t * N2 + n2, T1 * N2, N, inv2N)
-                                  : seq_chirp(k.post_hi, k.post_lo, true, t * N2 + n2, T1 * N2, N, inv2N, k.amp_turns);
+        ChirpSeq<R> c(MODE == MODE_FWD
+                          ? seq_chirp(k.pre_hi, k.pre_lo, true, t * N2 + n2, T1 * N2, N, inv2N)
+                          : seq_chirp(k.post_hi, k.post_lo, true, t * N2 + n2, T1 * N2, N, inv2N, k.amp_turns));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if constexpr (MODE == MODE_FWD)
-                v[e] = cmul(v[e], chirp_at<R>(c, e));
+                v[e] = cmul(v[e], c.next());
             else
-                v[e] = cscale(cmul(cconj(v[e]), chirp_at<R>(c, e)), mag);
+                v[e] = cscale(cmul(cconj(v[e]), c.next()), mag);
         }
     }
 
@@ -82,15 +82,14 @@ __global__ __launch_bounds__(LB) void k_fs1(
         fft_lds<E>(v, lds, t, T1, args.sc1);
 
     // twiddle W_N^(n2 k1), k1 = t + T1 e: turns -(n2 t + e n2 T1) / N, the two
-    // integer products reduced exactly modulo N
+    // integer products reduced exactly modulo N (a chirp with C = 0)
     {
         const double A = -(double)(((int64_t)n2 * t) % N) / (double)N;
         const double B = -(double)(((int64_t)n2 * T1) % N) / (double)N;
+        ChirpSeq<R> w(ThreadChirp{A, B, 0.0});
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            double u = fma(B, (double)e, A);
-            v[e] = cmul(v[e], cis_turns_from<R>(frac_turns(u)));
-        }
+        for (int e = 0; e < E; ++e)
+            v[e] = cmul(v[e], w.next());
     }
 
     // transpose through LDS: slot sl position k1  ->  lanes along k1
@@ -157,16 +156,15 @@ __global__ __launch_bounds__(LB) void k_fs2(typename Vec<R>::T *__restrict__ out
     else
         fft_lds<E>(v, lds, t, T2, args.sc2);
 
-    const ThreadChirp c = MODE == MODE_FWD
-                              ? seq_chirp(k.post_hi, k.post_lo, true, k1 + N1 * t, N1 * T2, N, inv2N, k.amp_turns)
-                              : seq_chirp(k.pre_hi, k.pre_lo, true, k1 + N1 * t, N1 * T2, N, inv2N);
+    ChirpSeq<R> c(MODE == MODE_FWD ? seq_chirp(k.post_hi, k.post_lo, true, k1 + N1 * t, N1 * T2, N, inv2N, k.amp_turns)
+                                   : seq_chirp(k.pre_hi, k.pre_lo, true, k1 + N1 * t, N1 * T2, N, inv2N));
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         C<R> y;
         if constexpr (MODE == MODE_FWD)
-            y = cscale(cmul(v[e], chirp_at<R>(c, e)), mag);
+            y = cscale(cmul(v[e], c.next()), mag);
         else
-            y = cconj(cmul(v[e], chirp_at<R>(c, e)));
+            y = cconj(cmul(v[e], c.next()));
         Buf<R>::store(y, rio, voff, e * sstep);
     }
 }

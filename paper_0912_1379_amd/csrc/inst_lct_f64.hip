@@ -11,6 +11,12 @@ hipError_t dispatch_lct_f64(int E, const void *in, void *out, const LctArgs &a, 
     // instantiations with N / 16 >= 256 threads assume one signal per
     // work-group
     if (E == 16 && is_fixed_sched(a.sc, a.N, 16) && (a.N / 16 < 256 || a.S == 1)) {
+        // N = 4096: one signal of 256 threads per work-group, exchanged through
+        // LDS in real and imaginary halves (34.8 KiB), so that registers, not
+        // LDS, set how many work-groups share a CU
+        if (a.N == 4096 && bs == 256)
+            return launch_lct_t<double, 16, 4096, false, 256, true>(in, out, a, nb, bs,
+                                                                    (size_t)lds_elems(4096) * sizeof(double), s);
         switch (a.N) {
 #define X(n)                                                                                                         \
     case n:                                                                                                          \

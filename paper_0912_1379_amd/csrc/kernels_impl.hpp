@@ -87,6 +87,35 @@ __device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
     return cis_turns_from<R>(frac_turns(u));
 }
 
+// The chirp values c_e = cis(A + e B + e^2 C) of one thread, e = 0, 1, 2, ...
+// in order (next() once per e).  FP32: each from its phase (hardware
+// sine/cosine).  FP64: the library sine/cosine costs tens of FP64 operations
+// per call, so the sequence is walked by products instead,
+//   c_{e+1} = c_e d_e,  d_e = cis(B + (2e + 1) C),  d_{e+1} = d_e cis(2 C),
+// from three evaluations per thread; after e steps the relative error is about
+// e^2 / 2 rounding units (3e-14 at e = 15).
+template <typename R> struct ChirpSeq;
+template <> struct ChirpSeq<float> {
+    ThreadChirp p;
+    int e;
+    __device__ explicit ChirpSeq(const ThreadChirp &c) : p(c), e(0) {}
+    __device__ __forceinline__ C<float> next() { return chirp_at<float>(p, e++); }
+};
+template <> struct ChirpSeq<double> {
+    C<double> c, d, r;
+    __device__ explicit ChirpSeq(const ThreadChirp &p)
+        : c(cis_turns(p.A)), d(cis_turns(frac_turns(p.B + p.C))), r(cis_turns(frac_turns(2.0 * p.C)))
+    {
+    }
+    __device__ __forceinline__ C<double> next()
+    {
+        const C<double> o = c;
+        c = cmul(c, d);
+        d = cmul(d, r);
+        return o;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // LCT forward (MODE_FWD) / adjoint (MODE_ADJ).  Per-signal constants come from
 // args.k (one matrix for the batch) or are derived from M4[sig].
@@ -94,9 +123,12 @@ __device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
 //   adjoint: L^H g = conj(pre (DFT(post conj(g)))) (the DFT matrix is symmetric).
 // ---------------------------------------------------------------------------
 // MF: radix-16 stages on the matrix cores (FP32 data, E = 16, split-BF16
-// products; see mfma_fft.hpp).
-template <typename R, int E, int NFIX, int MODE, bool MF = false, int LB = max_block(sizeof(R) == 8, E)>
-__global__ __launch_bounds__(LB) void k_lct(
+// products; see mfma_fft.hpp).  HX (fixed lengths): LDS exchanges in real and
+// imaginary halves, lds_elems(N) R of LDS per signal, and at least three waves
+// per SIMD asked of the register allocation.
+template <typename R, int E, int NFIX, int MODE, bool MF = false, int LB = max_block(sizeof(R) == 8, E),
+          bool HX = false>
+__global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, LctArgs args)
 {
     using V = typename Vec<R>::T;
@@ -150,23 +182,22 @@ __global__ __launch_bounds__(LB) void k_lct(
     if (k.b0) {
         // b = 0 (§1): a diagonal, no DFT.  Write it now and join the FFT
         // with zeros so the work-group's barriers stay uniform.
-        const ThreadChirp cb = thread_chirp(k.post_hi, k.post_lo, false, t, T, N, inv2N, k.amp_turns);
+        ChirpSeq<R> cb(thread_chirp(k.post_hi, k.post_lo, false, t, T, N, inv2N, k.amp_turns));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            C<R> f = cscale(chirp_at<R>(cb, e), mag);
+            C<R> f = cscale(cb.next(), mag);
             Buf<R>::store(cmul(v[e], MODE == MODE_FWD ? f : cconj(f)), rout, voff, e * sstep);
             v[e] = C<R>{(R)0, (R)0};
         }
     } else {
-        const ThreadChirp cin = MODE == MODE_FWD
-                                    ? thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N)
-                                    : thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns);
+        ChirpSeq<R> cin(MODE == MODE_FWD ? thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N)
+                                         : thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if constexpr (MODE == MODE_FWD)
-                v[e] = cmul(v[e], chirp_at<R>(cin, e));
+                v[e] = cmul(v[e], cin.next());
             else
-                v[e] = cscale(cmul(cconj(v[e]), chirp_at<R>(cin, e)), mag);
+                v[e] = cscale(cmul(cconj(v[e]), cin.next()), mag);
         }
     }
 
@@ -174,22 +205,24 @@ __global__ __launch_bounds__(LB) void k_lct(
         static_assert(E == 16 && sizeof(R) == 4 && NFIX == 0, "matrix-core stages: FP32, E = 16");
         fft_lds_mfma(v, smem, sl, t, T, N, lds_elems(N), args.sc);
     } else if constexpr (NFIX > 0) {
-        fft_lds_fixed<E, NFIX>(v, lds, t);
+        if constexpr (HX)
+            fft_lds_fixed_half<E, NFIX>(v, reinterpret_cast<R *>(smem_raw) + (size_t)sl * lds_elems(N), t);
+        else
+            fft_lds_fixed<E, NFIX>(v, lds, t);
     } else {
         fft_lds<E>(v, lds, t, T, args.sc);
     }
 
     if (live && !k.b0) {
-        const ThreadChirp cout = MODE == MODE_FWD
-                                     ? thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns)
-                                     : thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N);
+        ChirpSeq<R> cout(MODE == MODE_FWD ? thread_chirp(k.post_hi, k.post_lo, true, t, T, N, inv2N, k.amp_turns)
+                                          : thread_chirp(k.pre_hi, k.pre_lo, true, t, T, N, inv2N));
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             C<R> y;
             if constexpr (MODE == MODE_FWD)
-                y = cscale(cmul(v[e], chirp_at<R>(cout, e)), mag);
+                y = cscale(cmul(v[e], cout.next()), mag);
             else
-                y = cconj(cmul(v[e], chirp_at<R>(cout, e)));
+                y = cconj(cmul(v[e], cout.next()));
             Buf<R>::store(y, rout, voff, e * sstep);
         }
     }
@@ -425,11 +458,11 @@ __global__ __launch_bounds__(LB) void k_frft(
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-template <typename R, int E, int NFIX, bool MF = false, int LB = max_block(sizeof(R) == 8, E)>
+template <typename R, int E, int NFIX, bool MF = false, int LB = max_block(sizeof(R) == 8, E), bool HX = false>
 inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
                                hipStream_t s)
 {
-    auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD, MF, LB> : k_lct<R, E, NFIX, MODE_ADJ, MF, LB>;
+    auto kern = a.mode == MODE_FWD ? k_lct<R, E, NFIX, MODE_FWD, MF, LB, HX> : k_lct<R, E, NFIX, MODE_ADJ, MF, LB, HX>;
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
