@@ -259,7 +259,10 @@ void lct_ragged_plan_destroy(lct_ragged_plan p);
  * launches each after two warm-ups, on `batch` signals of scratch device
  * memory that it allocates and frees; batch 0 means about 2^24 samples),
  * records the fastest in the table and fills *res (may be NULL).  It
- * synchronises `stream`.  Entries are single text lines,
+ * synchronises `stream`.  A single-pass fractional-transform geometry serves
+ * both of its modes (an order per signal, and one order whose kernel spectrum
+ * is computed once), so there a candidate's time, and best_us / default_us,
+ * is the sum of one execution in each mode.  Entries are single text lines,
  *   lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16
  *   lct N=1048576 prec=fp32 N1=1024 E1=16 E2=16 C=16 RR=16 rad1=16.16.4 rad2=16.16.4
  * ("frft" for the fractional transform); every field is validated against

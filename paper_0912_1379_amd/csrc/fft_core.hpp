@@ -338,6 +338,26 @@ __device__ __forceinline__ int xcd_remap(int i, int n)
     return (i % X) * per + i / X;
 }
 
+// a mod m for 0 <= a < 2^24 and m >= 1, with m the same in every lane (a stage
+// stride, a transform length): a mask when m is a power of two; otherwise the
+// quotient is estimated as trunc(a * rcp(m)) in FP32 and the remainder
+// corrected exactly in integers.  The reciprocal (1 ulp) and the product (half
+// an ulp) put the estimate within (a/m) 1.5 2^-23 < 1 of a/m for a < 2^24 and
+// m >= 3, so one correction each way suffices; two are made below.  The
+// generic 32-bit remainder is a sequence of about thirty instructions.
+__device__ __forceinline__ int umod24(int a, int m)
+{
+    if ((m & (m - 1)) == 0)
+        return a & (m - 1);
+    const int q = (int)((float)a * __builtin_amdgcn_rcpf((float)m));
+    int r = a - q * m;
+    r += r < 0 ? m : 0;
+    r += r < 0 ? m : 0;
+    r -= r >= m ? m : 0;
+    r -= r >= m ? m : 0;
+    return r;
+}
+
 // LDS index with one pad element every 16 (breaks power-of-two bank strides).
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 __host__ __device__ constexpr int lds_elems(int N) { return N + (N >> 4) + 1; }
@@ -358,7 +378,7 @@ __device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
             u[r] = v[i + Q * r];
         if (Ns > 1) {
             int b = t + T * i;
-            int j = b % Ns;
+            int j = umod24(b, Ns);
             // base angle -j / (Ns RAD) turns (exact for power-of-two Ns RAD)
             const R inv = (R)1 / (R)(Ns * RAD);
             C<R> w[RAD];
@@ -412,7 +432,7 @@ __device__ __forceinline__ void stage_write(typename LdsElem<PART, R>::T *lds, c
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int b = t + T * i;
-        int j = b % Ns;
+        int j = umod24(b, Ns);
         int base = (b - j) * RAD + j;
         auto *p = lds + lds_pad(base);
         if ((Ns & 15) == 0) {

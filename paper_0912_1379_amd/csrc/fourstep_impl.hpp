@@ -84,8 +84,8 @@ __global__ __launch_bounds__(LB) void k_fs1(
     // twiddle W_N^(n2 k1), k1 = t + T1 e: turns -(n2 t + e n2 T1) / N, the two
     // integer products reduced exactly modulo N (a chirp with C = 0)
     {
-        const double A = -(double)(((int64_t)n2 * t) % N) / (double)N;
-        const double B = -(double)(((int64_t)n2 * T1) % N) / (double)N;
+        const double A = -(double)umod24(n2 * t, N) / (double)N;
+        const double B = -(double)umod24(n2 * T1, N) / (double)N;
         ChirpSeq<R> w(ThreadChirp{A, B, 0.0});
 #pragma unroll
         for (int e = 0; e < E; ++e)

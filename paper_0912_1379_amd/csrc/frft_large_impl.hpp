@@ -70,8 +70,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
     fft_lds<E>(v, lds, t, T1, a.sc1);
 
     {
-        const double A = -(double)(((int64_t)n2 * t) % L) / (double)L;
-        const double B = -(double)(((int64_t)n2 * T1) % L) / (double)L;
+        const double A = -(double)umod24(n2 * t, L) / (double)L;
+        const double B = -(double)umod24(n2 * T1, L) / (double)L;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             v[e] = cmul(v[e], cis_turns_from<R>(frac_turns(fma(B, (double)e, A))));
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(typename 
     for (int e = 0; e < E; ++e)
         v[e] = cconj(cmul(v[e], w[e]));
     fft_lds<E>(v, lds, t, T2, a.sc2);
-    const double A = -(double)(((int64_t)k1 * t) % L) / (double)L;
-    const double B = -(double)(((int64_t)k1 * T2) % L) / (double)L;
+    const double A = -(double)umod24(k1 * t, L) / (double)L;
+    const double B = -(double)umod24(k1 * T2, L) / (double)L;
 #pragma unroll
     for (int e = 0; e < E; ++e)
         stc<R>(R0 + (size_t)(t + T2 * e) * L1 + k1, cmul(v[e], cis_turns_from<R>(frac_turns(fma(B, (double)e, A)))));

@@ -189,8 +189,8 @@ __device__ __forceinline__ void rag_cols(const RagSize &z, int M, CF *smem, floa
         for (int e = 0; e < E1; ++e)
             v[e] = colok ? load((t + T1 * e) * N2 + n2, e) : CF{0.f, 0.f};
         fft_lds<E1>(v, lds, t, T1, z.sc1);
-        const double A = -(double)(((int64_t)n2 * t) % M) / (double)M;
-        const double B = -(double)(((int64_t)n2 * T1) % M) / (double)M;
+        const double A = -(double)umod24(n2 * t, M) / (double)M;
+        const double B = -(double)umod24(n2 * T1, M) / (double)M;
 #pragma unroll
         for (int e = 0; e < E1; ++e)
             v[e] = cmul(v[e], cis_turns_from<float>(frac_turns(fma(B, (double)e, A))));
@@ -270,8 +270,8 @@ __device__ __forceinline__ void rag_rows_conv(const RagSize &z, int M, CF *smem,
         fft_lds<E2>(v, lds, t, T2, z.sc2);
         // position n2 = t + T2 e: the inverse's twiddle W_M^(-n2 k1), applied to
         // the conjugate as W_M^(+n2 k1) = e^(-2 pi i n2 k1 / M)
-        const double A = -(double)(((int64_t)k1 * t) % M) / (double)M;
-        const double B = -(double)(((int64_t)k1 * T2) % M) / (double)M;
+        const double A = -(double)umod24(k1 * t, M) / (double)M;
+        const double B = -(double)umod24(k1 * T2, M) / (double)M;
         if (rowok) {
 #pragma unroll
             for (int e = 0; e < E2; ++e)

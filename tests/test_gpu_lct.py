@@ -127,6 +127,24 @@ def test_in_place_and_stream():
     assert torch.equal(y.cpu(), ref)
 
 
+@pytest.mark.parametrize("dtype,prec,N", [(torch.complex64, None, 4096), (torch.complex64, None, 16384),
+                                          (torch.complex128, None, 4096), (torch.complex128, None, 8192),
+                                          (torch.complex64, lct.LCT_FP32_SPLITBF16, 4096),
+                                          (torch.complex64, lct.LCT_FP32_SPLITBF16, 2048)])
+def test_in_place_equals_out_of_place(dtype, prec, N):
+    """Single-pass kernels read a whole signal before writing any of it, so out = in gives
+    the out-of-place result bit for bit (forward and adjoint)."""
+    M, f = c1_inputs(N, 5, 40 + N)
+    x = dev(f, dtype)
+    M4 = dev(M, torch.float64)
+    for fn in (lct.lct_exec_many, lct.lct_exec_many_adjoint):
+        ref = fn(x, M4, precision=prec)
+        x2 = x.clone()
+        y = fn(x2, M4, out=x2, precision=prec)
+        assert y.data_ptr() == x2.data_ptr()
+        assert torch.equal(y, ref), (fn.__name__, N, dtype, prec)
+
+
 def test_deterministic_repeat():
     N = 4096
     M, f = c1_inputs(N, 64, 6)
