@@ -168,7 +168,9 @@ int frft_exec_many(int64_t N, lct_precision prec, const double *Z2, const void *
  *    through 2 x 2N complex samples per signal (the data's and the kernel's
  *    spectra; the first also holds the inverse transform's intermediate).
  *    Required: without enough workspace the calls return LCT_ERR_WORKSPACE
- *    and do nothing.
+ *    and do nothing.  With one order for the batch (frft_exec_ws) the
+ *    kernel's spectrum is computed once, in the first signal's kernel
+ *    region, and read by every signal.
  *  - Single pass: 2N complex samples, optional.  frft_exec_ws with such a
  *    workspace computes the DFT of the Gaussian-chirp kernel once for the
  *    whole batch (its order is shared) and every signal reuses it: two
@@ -195,8 +197,8 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
  * of modulus <= 1; a matrix for which neither does (the sum would add and
  * cancel exponentially large terms) gives LCT_ERR_DOMAIN.  Real matrices
  * always qualify (unit-modulus chirps).  One matrix per call: its
- * convolution kernel's spectrum is shared by the batch when a single-pass
- * workspace is given.  Workspace, alignment and in != out as frft_exec_ws
+ * convolution kernel's spectrum is computed once for the batch when a
+ * workspace is given (always, for two-pass lengths).  Workspace, alignment and in != out as frft_exec_ws
  * (frft_workspace_size).  b == 0 and LCT_FP32_SPLITBF16 give
  * LCT_ERR_UNSUPPORTED.
  */

@@ -7,7 +7,10 @@
 // workspace holds two length-L regions per signal (R0 for v, R1 for t).
 // Launches: [pass 1: column DFTs of v and t, twiddled, stored transposed]
 // [pass 2: row DFTs of both, their product and the inverse transform's row
-// step, in place in R0] [pass 3: the inverse's column DFTs -> out].
+// step, in place in R0] [pass 3: the inverse's column DFTs -> out].  With one
+// order for the whole batch, t is transformed once: pass 1 runs its columns
+// for slot 0 only, a pass-2 launch finishes that spectrum in place in slot 0's
+// R1 (SPEC_WRITE), and the per-signal pass 2 reads it there (SPEC_READ).
 #pragma once
 #include "fourstep_impl.hpp"
 
@@ -112,19 +115,28 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(typename 
     const int r = tid % RR;
     const int t = tid / RR;
     const int k1 = k10 + r;
+    const bool write_spec = a.spec_mode == SPEC_WRITE; // launched over slot 0's rows only
     V *R0 = ws + (size_t)s * 2 * L;
-    const V *R1 = R0 + L;
+    V *R1 = a.spec_mode == SPEC_NONE ? R0 + L : ws + L;
 
     C<R> v[E], w[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const size_t i = (size_t)(t + T2 * e) * L1 + k1;
-        v[e] = ldc<R>(R0 + i);
+        if (!write_spec)
+            v[e] = ldc<R>(R0 + i);
         w[e] = ldc<R>(R1 + i);
     }
     C<R> *lds = smem + (size_t)r * lds_elems(a.L2);
+    if (a.spec_mode != SPEC_READ)
+        fft_lds<E>(w, lds, t, T2, a.sc2);
+    if (write_spec) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            stc<R>(R1 + (size_t)(t + T2 * e) * L1 + k1, w[e]);
+        return;
+    }
     fft_lds<E>(v, lds, t, T2, a.sc2);
-    fft_lds<E>(w, lds, t, T2, a.sc2);
 #pragma unroll
     for (int e = 0; e < E; ++e)
         v[e] = cconj(cmul(v[e], w[e]));

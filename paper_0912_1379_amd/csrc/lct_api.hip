@@ -329,9 +329,21 @@ int frft_large_launch(const FsTiling &f, int64_t N, bool fp64, const double *Z2,
     const int64_t nb1 = batch * (f.N2 / f.C), nb2 = batch * (f.N1 / f.RR);
     if (2 * nb1 > INT32_MAX || nb2 > INT32_MAX || batch > INT32_MAX)
         return LCT_ERR_ARG;
+    // one order for the batch: the kernel sequence is transformed once (its
+    // column pass for slot 0 only, then its row pass in place there)
+    const bool shared = Z2 == nullptr && k != nullptr && !k->special;
+    const int64_t nk1 = shared ? f.N2 / f.C : nb1;
     hipError_t e;
-    if ((e = launch_frl1(fp64, f.E1, in, ws, a, (int)(2 * nb1), f.bs1, f.lds1, s)) != hipSuccess ||
-        (e = launch_frl2(fp64, f.E2, ws, a, (int)nb2, f.bs2, f.lds2, s)) != hipSuccess ||
+    if ((e = launch_frl1(fp64, f.E1, in, ws, a, (int)(nb1 + nk1), f.bs1, f.lds1, s)) != hipSuccess)
+        return LCT_ERR_HIP;
+    if (shared) {
+        FrLArgs w = a;
+        w.spec_mode = SPEC_WRITE;
+        if ((e = launch_frl2(fp64, f.E2, ws, w, f.N1 / f.RR, f.bs2, f.lds2, s)) != hipSuccess)
+            return LCT_ERR_HIP;
+        a.spec_mode = SPEC_READ;
+    }
+    if ((e = launch_frl2(fp64, f.E2, ws, a, (int)nb2, f.bs2, f.lds2, s)) != hipSuccess ||
         (e = launch_frl3(fp64, f.E1, ws, out, a, (int)nb1, f.bs1, f.lds1, s)) != hipSuccess)
         return LCT_ERR_HIP;
     if (Z2 != nullptr || (k && k->special))

@@ -91,6 +91,7 @@ struct FrLArgs {
     const double *Z2;
     FrConst k;
     Sched sc1, sc2;
+    int spec_mode; // pass 2: SPEC_NONE, or one order for the batch (SPEC_WRITE once, then SPEC_READ)
 };
 // FP32 with the radix-16 stages on the matrix cores (E = 16 only).
 hipError_t launch_lct_mf(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,

@@ -491,6 +491,32 @@ def test_frft_two_pass(dtype, tol, N):
         assert rel_rows(y[s][rows], ref)[0] <= tol, (N, z)
 
 
+@pytest.mark.parametrize("dtype,tol,N", [(torch.complex64, 2e-5, 16384), (torch.complex64, 2e-5, 24576),
+                                         (torch.complex128, 1e-11, 5120)])
+def test_frft_two_pass_shared_order(dtype, tol, N):
+    """Two-pass lengths with one order for the batch: the kernel's spectrum is transformed once
+    (slot 0 of the workspace) and read by every signal.  Against the oracle on each signal's
+    energy rows, and against the per-signal-order path with the same order everywhere (its
+    constants are formed on the device, the shared ones on the host: equal to rounding)."""
+    prec = lct.LCT_FP64 if dtype == torch.complex128 else lct.LCT_FP32
+    B = 4
+    gen = np.random.default_rng(700 + N)
+    gp = workloads.gaussian_params(B, gen)
+    x = dev(workloads.chirped_gaussians(oracle.nodes(N), gp), dtype)
+    fin = x.cpu().numpy().astype(np.complex128)
+    p = lct.lct_plan_create(N, 1.0, 1.0, 0.0, 1.0, precision=prec)
+    ws = torch.full((lct.frft_workspace_size(N, prec, B),), 255, dtype=torch.uint8, device="cuda")
+    for z in [0.6 * np.exp(-1.1j), -0.7 + 0.2j, 1j, -1.0]:
+        print(f"[frft2-shared] N={N} {dtype} z={z}", flush=True)
+        y = lct.frft_exec(p, z, x, ws=ws).cpu().numpy().astype(np.complex128)
+        Z2 = dev(np.tile([[np.real(z), np.imag(z)]], (B, 1)), torch.float64)
+        y3 = lct.frft_exec_many(x, Z2).cpu().numpy().astype(np.complex128)
+        for s in range(B):
+            assert rel_rows(y[s], y3[s])[0] <= tol / 4, (N, z, s)
+        rows = frft_peak_rows(gp[0], z, N, 64, 0) if abs(z) < 1 or z.imag != 0 else np.arange(0, N, N // 64)
+        assert rel_rows(y[0][rows], oracle.frft(fin[0], z, rows=rows))[0] <= tol, (N, z)
+
+
 def test_frft_two_pass_needs_workspace():
     N = 16384
     x = torch.zeros(1, N, dtype=torch.complex64, device="cuda")
