@@ -27,8 +27,8 @@ __device__ __forceinline__ FrConst fr_const_of(const FrLArgs &a, int64_t s)
 // Pass 1 over columns n2 of the length-L sequence (element i = n1 L2 + n2).
 // blockIdx.x < batch * tiles handles the data (FR_DATA), the rest the
 // kernel sequence (FR_KERN).
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_frl1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
     using V = typename Vec<R>::T;
@@ -100,8 +100,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl1(
 //   sum_k P_k W_L^(-n k) = sum_k1 W_L1^(-n1 k1) [W_L^(-n2 k1) sum_k2 W_L2^(-n2 k2) P_(k1 + L1 k2)],
 // and the conjugate of the bracket (the forward length-L2 DFT of conj(P),
 // times W_L^(+n2 k1), W_L = e^(-2 pi i / L)) is stored into R0 at n2 L1 + k1.
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(typename Vec<R>::T *__restrict__ ws, FrLArgs a)
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_frl2(typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -153,8 +153,8 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl2(typename 
 // j = n2 + L2 n1; transposed through LDS (consecutive threads, consecutive j)
 // it is conjugated, multiplied by the diagonal and the constant, and the
 // first N outputs are stored.
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_frl3(const typename Vec<R>::T *__restrict__ ws,
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+__global__ __launch_bounds__(LB) void k_frl3(const typename Vec<R>::T *__restrict__ ws,
                                                                        typename Vec<R>::T *__restrict__ out, FrLArgs a)
 {
     using V = typename Vec<R>::T;
@@ -216,11 +216,20 @@ __global__ void k_fr_special(const typename Vec<R>::T *__restrict__ in, typename
     }
 }
 
+// The default widths (E = 16 FP32, 8 FP64) also have an instantiation bounded
+// at 256 threads, used whenever the work-group fits it: with the 1024-thread
+// bound the pass-2 kernel, which holds a data row and a kernel row per thread,
+// is held to 128 registers and spills.
+template <typename R, int E> constexpr bool has_tight_frl() { return E == (sizeof(R) == 8 ? 8 : 16); }
+
 template <typename R, int E>
 inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl1<R, E>;
+    if constexpr (has_tight_frl<R, E>())
+        if (bs <= 256)
+            kern = k_frl1<R, E, 256>;
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)in, (V *)ws, a);
@@ -232,6 +241,9 @@ inline hipError_t launch_frl2_t(void *ws, const FrLArgs &a, int nb, int bs, size
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl2<R, E>;
+    if constexpr (has_tight_frl<R, E>())
+        if (bs <= 256)
+            kern = k_frl2<R, E, 256>;
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (V *)ws, a);
@@ -244,6 +256,9 @@ inline hipError_t launch_frl3_t(const void *ws, void *out, const FrLArgs &a, int
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl3<R, E>;
+    if constexpr (has_tight_frl<R, E>())
+        if (bs <= 256)
+            kern = k_frl3<R, E, 256>;
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)ws, (V *)out, a);

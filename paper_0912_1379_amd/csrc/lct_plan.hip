@@ -274,13 +274,16 @@ FsTiling mfma_fs(int64_t N)
 
 namespace {
 
-FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap)
+// max_threads bounds each pass's work-group (columns or rows times threads
+// per column or row).
+FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap, int max_threads = 1024)
 {
     const int64_t N2 = N / N1;
     if (!E1 || !E2)
         return FsTiling{};
-    const int C = pick_group((int)N1, (int)(N1 / E1), E1, (int)N2, fp64, cap);
-    const int RR = pick_group((int)N2, (int)(N2 / E2), E2, (int)N1, fp64, cap);
+    const int T1 = (int)(N1 / E1), T2 = (int)(N2 / E2);
+    const int C = pick_group((int)N1, T1, E1, (int)N2, fp64, std::min(cap, std::max(1, max_threads / T1)));
+    const int RR = pick_group((int)N2, T2, E2, (int)N1, fp64, std::min(cap, std::max(1, max_threads / T2)));
     if (!C || !RR)
         return FsTiling{};
     return fs_of(N, fp64, (int)N1, E1, E2, C, RR, greedy_sched(N1, E1, 16, false), greedy_sched(N2, E2, 16, false));
@@ -288,8 +291,11 @@ FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap)
 
 } // namespace
 
-// N = N1 N2 with N1 the largest divisor <= sqrt(N) whose tiles fit.
-FsTiling default_fs(int64_t N, bool fp64)
+// N = N1 N2 with N1 the largest divisor <= sqrt(N) whose tiles fit.  For the
+// fractional transform's convolution (frft) work-groups stay within 256
+// threads: its pass-2 kernel holds two rows' values per thread and has a
+// 256-thread instantiation whose register budget fits them.
+FsTiling default_fs(int64_t N, bool fp64, bool frft)
 {
     int64_t best = 0;
     for (int64_t d = 1; d * d <= N; ++d)
@@ -301,7 +307,9 @@ FsTiling default_fs(int64_t N, bool fp64)
         const int64_t N2 = N / N1;
         if (N1 > single_pass_limit(fp64) || N2 > single_pass_limit(fp64))
             break;
-        FsTiling f = fs_for_split(N, fp64, N1, choose_E(N1, fp64, false), choose_E(N2, fp64, false), 64);
+        // (FP64 fractional pass 2 takes the width with the 256-thread instantiation)
+        FsTiling f = fs_for_split(N, fp64, N1, choose_E(N1, fp64, false), choose_E(N2, fp64, frft), 64,
+                                  frft ? 256 : 1024);
         if (f.ok)
             return f;
     }
@@ -339,7 +347,7 @@ void tiling_candidates(int64_t Nfft, bool fp64, bool frft, Tiling *out, int *n, 
     }
 }
 
-void fs_candidates(int64_t Nfft, bool fp64, FsTiling *out, int *n, int cap)
+void fs_candidates(int64_t Nfft, bool fp64, bool frft, FsTiling *out, int *n, int cap)
 {
     *n = 0;
     auto push = [&](const FsTiling &f) {
@@ -351,7 +359,7 @@ void fs_candidates(int64_t Nfft, bool fp64, FsTiling *out, int *n, int cap)
                 return;
         out[(*n)++] = f;
     };
-    push(default_fs(Nfft, fp64));
+    push(default_fs(Nfft, fp64, frft));
     // splits nearest to sqrt(N) in log distance, both factors within one pass
     std::vector<std::pair<double, int64_t>> splits;
     for (int64_t d = 2; d * 2 <= Nfft; ++d)
@@ -364,8 +372,11 @@ void fs_candidates(int64_t Nfft, bool fp64, FsTiling *out, int *n, int cap)
             break;
         const int64_t N1 = sp.second, N2 = Nfft / N1;
         const int e1 = choose_E(N1, fp64, false), e2 = choose_E(N2, fp64, false);
-        for (int cap : {64, 32, 16, 8, 4})
+        for (int cap : {64, 32, 16, 8, 4}) {
             push(fs_for_split(Nfft, fp64, N1, e1, e2, cap));
+            if (frft)
+                push(fs_for_split(Nfft, fp64, N1, e1, e2, cap, 256));
+        }
         for (int E1 : E_WIDTHS)
             for (int E2 : E_WIDTHS) {
                 if ((E1 != e1 && E1 * 2 != e1) || (E2 != e2 && E2 * 2 != e2))
@@ -572,7 +583,7 @@ FsTiling select_fs(int kind, int64_t N, int64_t Nfft, bool fp64)
     TuneEntry e;
     if (lookup(kind, N, fp64, &e) && e.two_pass && e.f.ok)
         return e.f;
-    return default_fs(Nfft, fp64);
+    return default_fs(Nfft, fp64, kind == LCT_TUNE_FRFT);
 }
 
 } // namespace lctk
@@ -645,7 +656,7 @@ int lct_tune_candidates(int64_t N, lct_precision prec, int kind, char *buf, size
         }
     } else {
         FsTiling c[MAX_CAND];
-        fs_candidates(Nfft, fp64, c, &n, MAX_CAND);
+        fs_candidates(Nfft, fp64, kind == LCT_TUNE_FRFT, c, &n, MAX_CAND);
         for (int i = 0; i < n; ++i) {
             TuneEntry e;
             e.two_pass = true;
@@ -691,7 +702,7 @@ int lct_tune_get(int64_t N, lct_precision prec, int kind, char *buf, size_t cap)
         // the heuristic's choice
         e.two_pass = Nfft > single_pass_limit(fp64);
         if (e.two_pass)
-            e.f = default_fs(Nfft, fp64);
+            e.f = default_fs(Nfft, fp64, kind == LCT_TUNE_FRFT);
         else
             e.t = default_tiling(Nfft, fp64, kind == LCT_TUNE_FRFT, 0);
     }
@@ -840,7 +851,7 @@ int lct_autotune(int64_t N, lct_precision prec, int kind, int64_t batch, hipStre
         }
     } else {
         FsTiling c[MAX_CAND];
-        fs_candidates(Nfft, fp64, c, &ncand, MAX_CAND);
+        fs_candidates(Nfft, fp64, kind == LCT_TUNE_FRFT, c, &ncand, MAX_CAND);
         for (int i = 0; i < ncand; ++i) {
             const FsTiling &f = c[i];
             const double us = time_it(

@@ -42,7 +42,7 @@ FsTiling fs_of(int64_t N, bool fp64, int N1, int E1, int E2, int C, int RR, cons
 
 // Built-in heuristic choices.
 Tiling default_tiling(int64_t Nfft, bool fp64, bool frft, size_t extra);
-FsTiling default_fs(int64_t N, bool fp64);
+FsTiling default_fs(int64_t N, bool fp64, bool frft = false);
 
 // The geometry the entry points use: the autotuner's entry for (transform
 // kind, signal length, precision) when one is recorded and valid, otherwise
@@ -59,7 +59,7 @@ FsTiling mfma_fs(int64_t N);
 
 // Enumerates the candidate geometries the autotuner times.
 void tiling_candidates(int64_t Nfft, bool fp64, bool frft, Tiling *out, int *n, int cap);
-void fs_candidates(int64_t Nfft, bool fp64, FsTiling *out, int *n, int cap);
+void fs_candidates(int64_t Nfft, bool fp64, bool frft, FsTiling *out, int *n, int cap);
 
 // Launches with an explicit geometry (host checks of pointers and sizes are
 // the caller's).
