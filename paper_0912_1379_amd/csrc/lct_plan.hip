@@ -293,21 +293,39 @@ FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap,
 
 // N = N1 N2 with N1 the largest divisor <= sqrt(N) whose tiles fit.  For the
 // fractional transform's convolution (frft) work-groups stay within 256
-// threads: its pass-2 kernel holds two rows' values per thread and has a
-// 256-thread instantiation whose register budget fits them.
+// threads, and pass 2, which holds a row of the data's and of the kernel's
+// values per thread, takes a factor whose width has the 256-thread
+// instantiation (16 FP32, 8 FP64) and, when both factors do, the shorter one.
 FsTiling default_fs(int64_t N, bool fp64, bool frft)
 {
     int64_t best = 0;
     for (int64_t d = 1; d * d <= N; ++d)
         if (N % d == 0)
             best = d;
+    if (frft) {
+        const int tight = fp64 ? 8 : 16;
+        for (int64_t d = best; d >= 2; --d) {
+            if (N % d)
+                continue;
+            for (const int64_t N2 : {d, N / d}) {
+                const int64_t N1 = N / N2;
+                if (N1 > single_pass_limit(fp64) || N2 > single_pass_limit(fp64))
+                    continue;
+                const int E2 = choose_E(N2, fp64, true);
+                if (E2 != tight)
+                    continue;
+                FsTiling f = fs_for_split(N, fp64, N1, choose_E(N1, fp64, false), E2, 64, 256);
+                if (f.ok)
+                    return f;
+            }
+        }
+    }
     for (int64_t N1 = best; N1 >= 2; --N1) {
         if (N % N1)
             continue;
         const int64_t N2 = N / N1;
         if (N1 > single_pass_limit(fp64) || N2 > single_pass_limit(fp64))
             break;
-        // (FP64 fractional pass 2 takes the width with the 256-thread instantiation)
         FsTiling f = fs_for_split(N, fp64, N1, choose_E(N1, fp64, false), choose_E(N2, fp64, frft), 64,
                                   frft ? 256 : 1024);
         if (f.ok)
