@@ -33,11 +33,38 @@ KERNEL_SOURCES = ["paper_0912_1379_amd/csrc/fft_core.hpp", "paper_0912_1379_amd/
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lct_fp32_n4096_b4096_traffic.json")
 
 
+def code_text(src: str) -> str:
+    """C++ source without comments and whitespace (string and character
+    literals kept): edits to comments or layout leave it unchanged."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_hash() -> str:
+    """Hash of the headline kernel's code (its three headers, comments and
+    whitespace removed), recorded beside the traffic counters taken for it."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

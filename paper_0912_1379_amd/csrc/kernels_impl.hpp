@@ -92,8 +92,9 @@ __device__ __forceinline__ C<R> chirp_at(const ThreadChirp &c, int e)
 // sine/cosine).  FP64: the library sine/cosine costs tens of FP64 operations
 // per call, so the sequence is walked by products instead,
 //   c_{e+1} = c_e d_e,  d_e = cis(B + (2e + 1) C),  d_{e+1} = d_e cis(2 C),
-// from three evaluations per thread; after e steps the relative error is about
-// e^2 / 2 rounding units (3e-14 at e = 15).
+// from three evaluations per thread; after e steps the error is about 2 e^2
+// rounding units (4e-14 at e = 15), half that of summing the phase polynomial
+// in FP64 for each value, whose rounding grows with e^2 |C| turns.
 template <typename R> struct ChirpSeq;
 template <> struct ChirpSeq<float> {
     ThreadChirp p;
