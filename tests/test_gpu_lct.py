@@ -515,6 +515,10 @@ def test_frft_two_pass_shared_order(dtype, tol, N):
             assert rel_rows(y[s], y3[s])[0] <= tol / 4, (N, z, s)
         rows = frft_peak_rows(gp[0], z, N, 64, 0) if abs(z) < 1 or z.imag != 0 else np.arange(0, N, N // 64)
         assert rel_rows(y[0][rows], oracle.frft(fin[0], z, rows=rows))[0] <= tol, (N, z)
+        # one signal: its workspace slot holds both its data and the shared spectrum
+        ws1 = torch.full((lct.frft_workspace_size(N, prec, 1),), 255, dtype=torch.uint8, device="cuda")
+        y1 = lct.frft_exec(p, z, x[:1], ws=ws1).cpu().numpy().astype(np.complex128)
+        assert np.array_equal(y1[0], y[0]), (N, z)
 
 
 def test_frft_two_pass_needs_workspace():
