@@ -297,9 +297,10 @@ FsTiling fs_for_split(int64_t N, bool fp64, int64_t N1, int E1, int E2, int cap,
 // N = N1 N2 with N1 the largest divisor <= sqrt(N) whose tiles fit.  The
 // work-groups hold about 256 threads but at least four columns (rows), i.e.
 // output segments of 32 bytes or more: timed against every candidate at
-// 2^14..2^24 this came within 7.5% of the fastest except at the shortest
-// lengths, where 1024-thread groups of 16 columns (the tile-width bound alone)
-// were up to 25% slower.  For the fractional transform's convolution (frft)
+// 2^14..2^24 this came within 7.5% of the fastest at all lengths but one
+// (FP64 2^14: 12.6%, where the geometry did not change), while the 1024-thread
+// groups of 16 columns that the tile-width bound alone gives were up to 25%
+// slower.  For the fractional transform's convolution (frft)
 // the work-groups stay within 256 threads, and pass 2, which holds a row of
 // the data's and of the kernel's values per thread, takes a factor whose width
 // has the 256-thread instantiation (16 FP32, 8 FP64), the shorter one when
