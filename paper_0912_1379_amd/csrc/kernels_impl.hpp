@@ -360,9 +360,13 @@ __device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const 
 }
 
 // LFIX > 0: the convolution length L = 2N = LFIX with its compile-time radix
-// schedule.
-template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
-__global__ __launch_bounds__(LB) void k_frft(
+// schedule.  SREAD: the instantiation for a spectrum shared by the batch
+// (SPEC_READ), which reads it from the workspace at the product instead of
+// holding it in registers through the data's FFT; with those registers free
+// it is asked for four waves per SIMD (two 512-thread work-groups per CU at
+// L = 8192, against one for the kernel that transforms its own spectrum).
+template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool SREAD = false>
+__global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FrArgs args)
 {
     using V = typename Vec<R>::T;
@@ -398,7 +402,9 @@ __global__ __launch_bounds__(LB) void k_frft(
     // with one order for the whole batch the DFT is computed once (SPEC_WRITE)
     // and loaded by every signal (SPEC_READ), in natural order p = t + T e
     C<R> K[E];
-    if (args.spec_mode == SPEC_READ) {
+    if constexpr (SREAD) {
+        // the spectrum is read at the product below
+    } else if (args.spec_mode == SPEC_READ) {
         const V *sp = reinterpret_cast<const V *>(args.spec);
 #pragma unroll
         for (int e = 0; e < E; ++e)
@@ -439,9 +445,16 @@ __global__ __launch_bounds__(LB) void k_frft(
     fft_any<R, E, LFIX>(v, lds, t, T, sc);
 
     // 3) inverse DFT of the product: conj(FFT(conj(V K)))
+    if constexpr (SREAD) {
+        const V *sp = reinterpret_cast<const V *>(args.spec);
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        v[e] = cconj(cmul(v[e], K[e]));
+        for (int e = 0; e < E; ++e)
+            v[e] = cconj(cmul(v[e], ldc<R>(sp + t + T * e)));
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = cconj(cmul(v[e], K[e]));
+    }
     fft_any<R, E, LFIX>(v, lds, t, T, sc);
 
     if (live && !k.special) {
@@ -488,6 +501,9 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
                                 hipStream_t s)
 {
     auto kern = k_frft<R, E, LFIX, LB>;
+    if constexpr (LFIX > 0 && sizeof(R) == 4)
+        if (a.spec_mode == SPEC_READ)
+            kern = k_frft<R, E, LFIX, LB, true>;
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
