@@ -50,59 +50,77 @@ void parallel_ranges(int64_t n, F body)
         t.join();
 }
 
-// Eigenvalues of the symmetric tridiagonal matrix H of §2 (zero diagonal,
-// off-diagonal sqrt(i / 2), i = 1 .. N-1), i.e. the zeros of H_N, by the QL
-// algorithm with implicit Wilkinson shifts (eigenvalues only, O(N^2)).
-// Returns them ascending in d.
-void tridiag_zeros(int64_t N, std::vector<double> &d)
+// One implicit symmetric QR step with a Wilkinson shift on the unreduced
+// block [lo, hi] of a symmetric tridiagonal matrix (diagonal al, off-diagonal
+// be, be[i] coupling i and i + 1), as in Golub & Van Loan, "Matrix
+// Computations", the implicit symmetric QR step (Algorithm 8.3.2): the shift
+// mu is the eigenvalue of the trailing 2 x 2 block nearer its last diagonal
+// entry; a plane rotation in (lo, lo + 1) taken from the first column of
+// T - mu I creates a bulge below the subdiagonal, and rotations in
+// (k, k + 1), k = lo + 1 .. hi - 1, chase it off the bottom.  Each rotation
+// is applied as a similarity T <- G^T T G to the 2 x 2 diagonal block it
+// touches and to its two neighbouring couplings.
+void qr_step_wilkinson(double *al, double *be, int64_t lo, int64_t hi)
 {
-    d.assign((size_t)N, 0.0);
-    std::vector<double> e((size_t)N, 0.0); // e[i] couples i and i + 1
-    for (int64_t i = 0; i + 1 < N; ++i)
-        e[(size_t)i] = sqrt((double)(i + 1) / 2.0);
-    for (int64_t l = 0; l < N; ++l) {
-        for (int iter = 0; iter < 60; ++iter) {
-            int64_t m = l;
-            for (; m + 1 < N; ++m) {
-                const double dd = fabs(d[(size_t)m]) + fabs(d[(size_t)m + 1]);
-                if (fabs(e[(size_t)m]) <= 2.3e-16 * dd || e[(size_t)m] == 0.0)
-                    break;
-            }
-            if (m == l)
-                break;
-            // Wilkinson shift from the leading 2 x 2 block at l
-            double g = (d[(size_t)l + 1] - d[(size_t)l]) / (2.0 * e[(size_t)l]);
-            double r = sqrt(g * g + 1.0);
-            g = d[(size_t)m] - d[(size_t)l] + e[(size_t)l] / (g + (g >= 0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            int64_t i = m - 1;
-            bool split = false;
-            for (; i >= l; --i) {
-                const double f = s * e[(size_t)i], b = c * e[(size_t)i];
-                r = sqrt(f * f + g * g); // entries are O(sqrt(N)): no overflow
-                e[(size_t)i + 1] = r;
-                if (r == 0.0) {
-                    d[(size_t)i + 1] -= p;
-                    e[(size_t)m] = 0.0;
-                    split = true;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[(size_t)i + 1] - p;
-                r = (d[(size_t)i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[(size_t)i + 1] = g + p;
-                g = c * r - b;
-            }
-            if (split)
-                continue;
-            d[(size_t)l] -= p;
-            e[(size_t)l] = g;
-            e[(size_t)m] = 0.0;
+    const double half_gap = 0.5 * (al[hi - 1] - al[hi]);
+    const double last = be[hi - 1];
+    const double mu = al[hi] - last * last / (half_gap + copysign(hypot(half_gap, last), half_gap));
+    double x = al[lo] - mu; // entry to keep
+    double z = be[lo];      // entry to annihilate
+    for (int64_t k = lo; k < hi; ++k) {
+        // rotation [c s; -s c] with [c s; -s c]^T (x, z) = (r, 0)
+        double c = 1.0, s = 0.0;
+        if (z != 0.0) {
+            const double r = hypot(x, z);
+            c = x / r;
+            s = -z / r;
+            if (k > lo)
+                be[k - 1] = r; // the coupling that held the bulge's partner
+        }
+        const double p = al[k], q = al[k + 1], o = be[k];
+        const double cc = c * c, ss = s * s, cs = c * s;
+        al[k] = cc * p - 2.0 * cs * o + ss * q;
+        al[k + 1] = ss * p + 2.0 * cs * o + cc * q;
+        be[k] = cs * (p - q) + (cc - ss) * o;
+        if (k + 1 < hi) {
+            // the rotation spills into the coupling (k, k + 2): the next bulge
+            const double nxt = be[k + 1];
+            z = -s * nxt;
+            be[k + 1] = c * nxt;
+            x = be[k];
         }
     }
-    std::sort(d.begin(), d.end());
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix H of §2 (zero diagonal,
+// off-diagonal sqrt(i / 2), i = 1 .. N-1), i.e. the zeros of H_N, by the
+// symmetric QR algorithm (Golub & Van Loan, Algorithm 8.3.3): couplings
+// below eps (|al_i| + |al_{i+1}|) are set to zero, and implicit Wilkinson
+// steps run on the lowest unreduced block until the matrix is diagonal;
+// O(N^2) for the eigenvalues alone.  Returns them ascending in x.
+void tridiag_zeros(int64_t N, std::vector<double> &x)
+{
+    std::vector<double> al((size_t)N, 0.0), be((size_t)(N > 1 ? N - 1 : 1), 0.0);
+    for (int64_t i = 0; i + 1 < N; ++i)
+        be[(size_t)i] = sqrt((double)(i + 1) / 2.0);
+    const double eps = 0x1p-52;
+    int64_t hi = N - 1;
+    int64_t guard = 64 * (N + 1); // the shifted iteration needs about two steps per eigenvalue
+    while (hi > 0 && guard-- > 0) {
+        for (int64_t i = 0; i < hi; ++i)
+            if (fabs(be[(size_t)i]) <= eps * (fabs(al[(size_t)i]) + fabs(al[(size_t)i + 1])))
+                be[(size_t)i] = 0.0;
+        while (hi > 0 && be[(size_t)hi - 1] == 0.0)
+            --hi; // al[hi] has converged
+        if (hi == 0)
+            break;
+        int64_t lo = hi - 1;
+        while (lo > 0 && be[(size_t)lo - 1] != 0.0)
+            --lo;
+        qr_step_wilkinson(al.data(), be.data(), lo, hi);
+    }
+    x = al;
+    std::sort(x.begin(), x.end());
 }
 
 // Newton steps on the normalised Hermite function phi_N at each zero, with
