@@ -11,6 +11,8 @@
 // Pass 2 reads and writes exactly the same positions of `out` (the slots
 // k1 + N1 m, m < N2, of its own rows k1), so `out` holds the intermediate and
 // no workspace is needed; the input must not alias the output.
+// A signal with b = 0 (the diagonal of §1, no DFT) is finished by pass 1 and
+// skipped by pass 2.
 #pragma once
 #include "kernels_impl.hpp"
 
@@ -60,6 +62,19 @@ __global__ __launch_bounds__(LB) void k_fs1(
 
     const LctConst k = args.M4 != nullptr ? lct_const_from(args.nc, m4[0], m4[1], m4[2], m4[3]) : args.k;
     const R mag = (R)k.amp_mag;
+    if (k.b0) {
+        // b = 0 (§1): the diagonal sqrt(d) e^{i c x_i^2/(2d)} (conjugated for
+        // the adjoint) on this work-group's elements i = n1 N2 + n2, written in
+        // place of the transposed intermediate; pass 2 skips the signal.  One
+        // signal per work-group, so the whole group returns together.
+        ChirpSeq<R> c(seq_chirp(k.post_hi, k.post_lo, false, t * N2 + n2, T1 * N2, N, inv2N, k.amp_turns));
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<R> f = cscale(c.next(), mag);
+            Buf<R>::store(cmul(v[e], MODE == MODE_FWD ? f : cconj(f)), rout, voff, e * sstep);
+        }
+        return;
+    }
     {
         ChirpSeq<R> c(MODE == MODE_FWD
                           ? seq_chirp(k.pre_hi, k.pre_lo, true, t * N2 + n2, T1 * N2, N, inv2N)
@@ -147,6 +162,8 @@ __global__ __launch_bounds__(LB) void k_fs2(typename Vec<R>::T *__restrict__ out
 
     const LctConst k = args.M4 != nullptr ? lct_const_from(args.nc, m4[0], m4[1], m4[2], m4[3]) : args.k;
     const R mag = (R)k.amp_mag;
+    if (k.b0)
+        return; // pass 1 wrote the b = 0 diagonal (one signal per work-group)
 
     C<R> *lds = smem + (size_t)r * lds_elems(N2);
     if constexpr (MF)

@@ -446,6 +446,37 @@ def test_two_pass_adjoint_fp32():
     check_large(32768, torch.complex64, 1, 16, 2e-5, adjoint=True)
 
 
+@pytest.mark.parametrize("dtype,prec,N", [(torch.complex64, lct.LCT_FP32, 32768),
+                                          (torch.complex128, lct.LCT_FP64, 16384),
+                                          (torch.complex64, lct.LCT_FP32_SPLITBF16, 32768)])
+def test_two_pass_b_zero_rows(dtype, prec, N):
+    """b = 0 rows (the diagonal of §1) mixed into a batch at two-pass lengths, through
+    lct_exec_many and a plan, forward and adjoint: pass 1 writes the diagonal, pass 2
+    leaves those signals alone; the b != 0 rows around them are unaffected."""
+    B = 4
+    M, f = c1_inputs(N, B, 900 + N)
+    M[1] = [2.0, 0.0, 0.7, 0.5]
+    M[2] = [-0.5, 0.0, 1.2, -2.0]
+    x = dev(f, dtype)
+    M4 = dev(M, torch.float64)
+    fin = x.cpu().numpy().astype(np.complex128)
+    tol = 2e-4 if prec == lct.LCT_FP32_SPLITBF16 else TOL[dtype]
+    y = lct.lct_exec_many(x, M4, precision=prec).cpu().numpy()
+    ya = lct.lct_exec_many_adjoint(x, M4, precision=prec).cpu().numpy()
+    rows = np.sort(np.random.default_rng(N).choice(N, 64, replace=False))
+    for s in range(B):
+        if M[s][1] == 0.0:
+            assert rel_rows(y[s], oracle.lct(fin[s], *M[s]))[0] <= tol, s
+            # the adjoint of the diagonal is its conjugate
+            ref_a = np.conj(oracle.lct(np.conj(fin[s]), *M[s]))
+            assert rel_rows(ya[s], ref_a)[0] <= tol, s
+        else:
+            assert rel_rows(y[s][rows], oracle.lct(fin[s], *M[s], rows=rows))[0] <= tol, s
+    p = lct.lct_plan_create(N, *M[2], precision=prec)
+    y2 = lct.lct_exec(p, x[2:3].contiguous()).cpu().numpy()
+    assert rel_rows(y2[0], oracle.lct(fin[2], *M[2]))[0] <= tol
+
+
 def test_two_pass_rejects_in_place():
     x = torch.zeros(1, 32768, dtype=torch.complex64, device="cuda")
     M4 = torch.tensor([[1.0, 1.0, 0.0, 1.0]], dtype=torch.float64, device="cuda")
