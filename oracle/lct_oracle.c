@@ -40,6 +40,25 @@
 
 #define PI_L 3.141592653589793238462643383279502884L
 
+/* Compensated (Neumaier) summation in long double: the running sum s and the
+ * rounding error c of every addition so far; the sum is s + c.  Sums of 2^20
+ * terms then carry about one rounding of the result instead of up to 2^20. */
+typedef struct {
+    long double s, c;
+} ksum;
+
+static void ksum_add(ksum *k, long double v)
+{
+    long double t = k->s + v;
+    if (fabsl(k->s) >= fabsl(v))
+        k->c += (k->s - t) + v;
+    else
+        k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+static long double ksum_value(const ksum *k) { return k->s + k->c; }
+
 static long double node_l(int64_t N, int64_t k)
 {
     /* eq. (asymcer), 0-based: x_k = (2k - N + 1) pi / (2 sqrt(2N)) */
@@ -135,7 +154,7 @@ int oracle_lct_rows_scaled(int64_t N, double a, double b, double c, double d, do
         }
         int64_t nj = 2 * j - N + 1;
         long double t3 = B * D * (long double)nj * (long double)nj / ((long double)N * S * S);
-        long double sr = 0.0L, si = 0.0L;
+        ksum sr = {0.0L, 0.0L}, si = {0.0L, 0.0L};
         for (int64_t k = 0; k < N; ++k) {
             int64_t nk = 2 * k - N + 1;
             int64_t m = (nj * nk) % (4 * N);
@@ -147,10 +166,10 @@ int oracle_lct_rows_scaled(int64_t N, double a, double b, double c, double d, do
             s = sinl(ph);
             co = cosl(ph);
             long double fr = (long double)f[2 * k], fi = (long double)f[2 * k + 1];
-            sr += co * fr - s * fi;
-            si += co * fi + s * fr;
+            ksum_add(&sr, co * fr - s * fi);
+            ksum_add(&si, co * fi + s * fr);
         }
-        long double complex v = amp * CMPLXL(sr, si);
+        long double complex v = amp * CMPLXL(ksum_value(&sr), ksum_value(&si));
         out[2 * r] = (double)creall(v);
         out[2 * r + 1] = (double)cimagl(v);
     }
@@ -199,13 +218,15 @@ int oracle_lct_same_rows(int64_t N, double ar, double ai, double br, double bi, 
             continue;
         }
         const long double xj = node_l(N, j);
-        long double complex acc = 0;
+        ksum ar_ = {0.0L, 0.0L}, ai_ = {0.0L, 0.0L};
         for (int64_t k = 0; k < N; ++k) {
             const long double xk = node_l(N, k);
             const long double complex e = w * (A * xk * xk - 2.0L * xk * xj + D * xj * xj);
-            acc += cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+            const long double complex t = cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+            ksum_add(&ar_, creall(t));
+            ksum_add(&ai_, cimagl(t));
         }
-        const long double complex v = amp * acc;
+        const long double complex v = amp * CMPLXL(ksum_value(&ar_), ksum_value(&ai_));
         out[2 * r] = (double)creall(v);
         out[2 * r + 1] = (double)cimagl(v);
     }
@@ -233,7 +254,7 @@ int oracle_lct_adjoint(int64_t N, double a, double b, double c, double d,
         int64_t nk = 2 * k - N + 1;
         long double t1 = A * PI_L * PI_L * (long double)nk * (long double)nk /
                          (16.0L * B * (long double)N);
-        long double sr = 0.0L, si = 0.0L;
+        ksum sr = {0.0L, 0.0L}, si = {0.0L, 0.0L};
         for (int64_t j = 0; j < N; ++j) {
             int64_t nj = 2 * j - N + 1;
             int64_t m = (nj * nk) % (4 * N);
@@ -244,10 +265,10 @@ int oracle_lct_adjoint(int64_t N, double a, double b, double c, double d,
             long double ph = -(t1 - cross + t3); /* conjugate phase */
             long double s = sinl(ph), co = cosl(ph);
             long double gr = (long double)g[2 * j], gi = (long double)g[2 * j + 1];
-            sr += co * gr - s * gi;
-            si += co * gi + s * gr;
+            ksum_add(&sr, co * gr - s * gi);
+            ksum_add(&si, co * gi + s * gr);
         }
-        long double complex v = conjl(amp) * CMPLXL(sr, si);
+        long double complex v = conjl(amp) * CMPLXL(ksum_value(&sr), ksum_value(&si));
         out[2 * k] = (double)creall(v);
         out[2 * k + 1] = (double)cimagl(v);
     }
@@ -356,14 +377,16 @@ int oracle_frft_rows(int64_t N, double zr, double zi, const double *f,
             continue;
         }
         long double xj = node_l(N, j);
-        long double complex acc = 0;
+        ksum ar_ = {0.0L, 0.0L}, ai_ = {0.0L, 0.0L};
         for (int64_t k = 0; k < N; ++k) {
             long double xk = node_l(N, k);
             long double complex e =
                 -(opz2 * (xj * xj + xk * xk) - 4.0L * z * xj * xk) / (2.0L * omz2);
-            acc += cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+            long double complex t = cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+            ksum_add(&ar_, creall(t));
+            ksum_add(&ai_, cimagl(t));
         }
-        long double complex v = pref * acc;
+        long double complex v = pref * CMPLXL(ksum_value(&ar_), ksum_value(&ai_));
         out[2 * r] = (double)creall(v);
         out[2 * r + 1] = (double)cimagl(v);
     }

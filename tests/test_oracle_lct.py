@@ -94,6 +94,28 @@ def test_chirped_gaussians_closed_form():
             assert relerr(G, ref) < 1e-10, (i, M[i], gp[i])
 
 
+def test_long_rows_match_closed_form_at_2_20():
+    """N = 2^20: rows of 2^20-term sums (compensated) near the transform's peak against the
+    Gaussian integral.  A resolved Gaussian makes the Riemann sum spectrally accurate, so
+    what is left is the summation's own rounding over a million terms."""
+    N = 1 << 20
+    x = oracle.nodes(N)
+    a, b, d = 0.8, 1.3, 0.9
+    c = (a * d - 1) / b
+    mu, sigma, kappa = 0.7, 1.1, 0.3
+    al = 1 / (2 * sigma ** 2) - 1j * kappa
+    be = -mu / (2 * sigma ** 2)
+    ga = mu ** 2 / (2 * sigma ** 2)
+    f = np.exp(-(al * x * x + 2 * be * x + ga))
+    y = oracle.output_nodes(N, b)
+    A = al - 1j * a / (2 * b)
+    peak = int(np.argmax(np.real((be + 1j * y / (2 * b)) ** 2 / A)))
+    rows = np.arange(peak - 24, peak + 24, 3)
+    G = oracle.lct(f, a, b, c, d, rows=rows)
+    ref = gaussian_lct(y[rows], al, be, ga, a, b, d)
+    assert relerr(G, ref) < 1e-13
+
+
 def hermite_gauss_lct(n, y, a, b, c, d):
     """Textbook identity: LCT of psi_n is rho^(-1/2) e^(-i(n+1/2)phi) psi_n(y/rho)
     e^(i(ac+bd) y^2 / (2 rho^2)) with a + i b = rho e^(i phi)."""
