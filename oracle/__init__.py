@@ -26,8 +26,10 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             and mpmath brute force.
 ``lct_adjoint``             conjugate transpose of the same matrix; pinned by
                             the inner-product identity and unitarity.
-``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d);
-                            pinned by central finite differences of ``lct``.
+``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d)
+                            (for b = 0, of the diagonal of §1: c and d
+                            enter, a and b do not); pinned by central finite
+                            differences of ``lct``.
 ``frft(f, z)``              same-grid Riemann sum of eqs. (fasy), (primcuad),
                             (cuadtrfor); pinned by the continuum eigen-identity
                             on Hermite functions, the z=+-i Fourier kernel of
@@ -179,7 +181,8 @@ def lct_adjoint(g, a: float, b: float, c: float, d: float) -> np.ndarray:
 
 
 def lct_param_grad(f, g, a: float, b: float, c: float, d: float) -> np.ndarray:
-    """(dl/da, dl/db, dl/dc, dl/dd) = Re sum_j conj(g_j) dG_j/dtheta."""
+    """(dl/da, dl/db, dl/dc, dl/dd) = Re sum_j conj(g_j) dG_j/dtheta; for b = 0 the
+    derivative of the diagonal of §1 (dl/da = dl/db = 0)."""
     f = _cplx_in(f)
     g = _cplx_in(g)
     N = f.shape[0]

@@ -285,14 +285,43 @@ int oracle_lct_adjoint(int64_t N, double a, double b, double c, double d,
  *   dPhi/da = x_k^2/(2b),  dPhi/db = -a x_k^2/(2 b^2) + 8 d x_j^2/pi^2,
  *   dPhi/dd = 8 b x_j^2 / pi^2,  amplitude h (2 pi i b)^(-1/2): d/db = -1/(2b).
  * c does not enter for b != 0, so dl/dc = 0.
- * Pinned: central finite differences of oracle_lct_rows.
+ *
+ * For b = 0 the transform is the diagonal of §1, G_j = sqrt(d) exp(i c x_j^2/(2d)) f_j
+ * (output nodes x_j / d moving with d, as y_j moves with b above):
+ *   dG_j/dc = i x_j^2/(2d) G_j,   dG_j/dd = (1/(2d) - i c x_j^2/(2 d^2)) G_j,
+ * and a, b do not enter that formula (a = 1/d there), so dl/da = dl/db = 0.
+ * The discrete b != 0 matrix does not tend to the diagonal as b -> 0 (its
+ * output nodes 4 b x_j / pi collapse to 0), so no derivative across b = 0 is
+ * defined.
+ * Pinned: central finite differences of oracle_lct_rows (in a, b, d for
+ * b != 0 with c following from ad - bc = 1; in c and d at b = 0).
  */
 int oracle_lct_param_grad(int64_t N, double a, double b, double c, double d,
                           const double *f, const double *g, double *grad4)
 {
-    (void)c;
-    if (N < 1 || f == NULL || g == NULL || grad4 == NULL || b == 0.0)
+    if (N < 1 || f == NULL || g == NULL || grad4 == NULL)
         return -1;
+    if (b == 0.0) {
+        if (d == 0.0)
+            return -1;
+        const long double C = (long double)c, D = (long double)d;
+        const long double complex sd = csqrtl(CMPLXL(D, 0.0L));
+        long double gc = 0.0L, gd = 0.0L;
+        for (int64_t j = 0; j < N; ++j) {
+            const long double xj = node_l(N, j);
+            const long double x2 = xj * xj;
+            const long double complex G = sd * cexpl(CMPLXL(0.0L, C * x2 / (2.0L * D))) *
+                                          CMPLXL((long double)f[2 * j], (long double)f[2 * j + 1]);
+            const long double complex gj = CMPLXL((long double)g[2 * j], (long double)g[2 * j + 1]);
+            gc += creall(conjl(gj) * CMPLXL(0.0L, x2 / (2.0L * D)) * G);
+            gd += creall(conjl(gj) * CMPLXL(1.0L / (2.0L * D), -C * x2 / (2.0L * D * D)) * G);
+        }
+        grad4[0] = 0.0;
+        grad4[1] = 0.0;
+        grad4[2] = (double)gc;
+        grad4[3] = (double)gd;
+        return 0;
+    }
     const long double h = PI_L / sqrtl(2.0L * (long double)N);
     const long double A = (long double)a, B = (long double)b, D = (long double)d;
     const long double complex amp = h * inv_sqrt_2pi_i_b(B);

@@ -371,6 +371,33 @@ def test_param_grad_finite_differences():
     assert grad[2] == 0.0
 
 
+@pytest.mark.parametrize("c,d", [(0.7, 0.5), (1.2, -2.0)])
+def test_param_grad_b_zero_finite_differences(c, d):
+    """b = 0: the gradient of the diagonal of §1 (c and d enter, a and b do not) vs central
+    differences of the forward oracle, for the loss l = sum |G - T|^2 (grad_G = 2 (G - T)),
+    whose phase dependence makes dl/dc nonzero; d < 0 takes the principal root."""
+    N = 64
+    x = oracle.nodes(N)
+    f = np.exp(-(x - 0.3) ** 2 / 2.0 + 0.2j * x * x)
+    g = np.random.default_rng(19)
+    T = g.standard_normal(N) + 1j * g.standard_normal(N)
+    a = 1.0 / d
+
+    def loss(c_, d_):
+        G = oracle.lct(f, a, 0.0, c_, d_)
+        return float(np.sum(np.abs(G - T) ** 2))
+
+    G = oracle.lct(f, a, 0.0, c, d)
+    grad = oracle.lct_param_grad(f, 2 * (G - T), a, 0.0, c, d)
+    eps = 1e-6
+    fd_c = (loss(c + eps, d) - loss(c - eps, d)) / (2 * eps)
+    fd_d = (loss(c, d + eps) - loss(c, d - eps)) / (2 * eps)
+    assert abs(grad[2] - fd_c) <= 1e-7 * max(1.0, abs(fd_c)), (grad, fd_c)
+    assert abs(grad[3] - fd_d) <= 1e-7 * max(1.0, abs(fd_d)), (grad, fd_d)
+    assert abs(fd_c) > 1e-2 and abs(fd_d) > 1e-2
+    assert grad[0] == 0.0 and grad[1] == 0.0
+
+
 def test_nodes_spacing_and_symmetry():
     """eq. (asymcer) and eq. (deltk): symmetric, equispaced with spacing pi/sqrt(2N)."""
     for N in [1, 2, 7, 128, 4096]:
