@@ -137,11 +137,18 @@ int lct_exec_many_adjoint(int64_t N, lct_precision prec, const double *M4, const
                           void *out, int64_t batch, hipStream_t stream);
 
 /*
- * Parameter gradient of a real loss l for the b != 0 transform, per signal:
+ * Parameter gradient of a real loss l, per signal:
  *   grad4[s] = (dl/da, dl/db, dl/dc, dl/dd),  dl/dtheta = Re sum_j conj(g_j) dG_j/dtheta,
- * g = dl/dRe G + i dl/dIm G (DEVICE, batch x N complex), f the forward input,
- * with the output nodes y_j moving with b.  dl/dc = 0 since c does not enter
- * for b != 0.  grad4 is DEVICE memory of batch x 4 doubles.
+ * g = dl/dRe G + i dl/dIm G (DEVICE, batch x N complex), f the forward input.
+ * b != 0: the Riemann sum of §1 with the output nodes y_j moving with b;
+ * dl/dc = 0 since c does not enter.  b == 0: the diagonal of §1,
+ * G_j = sqrt(d) e^{i c x_j^2/(2d)} f_j with output nodes x_j/d moving with d, so
+ * dl/da = dl/db = 0 and dl/dc, dl/dd are its derivatives (the discrete matrix
+ * has no derivative across b = 0: its nodes 4 b x_j / pi collapse there).
+ * The per-signal sums are reduced in a fixed order: results are reproducible
+ * bit for bit.  grad4 is DEVICE memory of batch x 4 doubles.  Single-pass
+ * lengths only (N <= lct_max_single_pass(prec)); longer ones give
+ * LCT_ERR_UNSUPPORTED.  LCT_FP32_SPLITBF16 gives LCT_ERR_UNSUPPORTED.
  */
 int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const void *f,
                         const void *g, double *grad4, int64_t batch, hipStream_t stream);
@@ -152,8 +159,9 @@ int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const v
  *   out[j] = sum_k h sqrt(2/(1-z^2)) exp(-[(1+z^2)(x_j^2+x_k^2) - 4 z x_j x_k]/(2(1-z^2))) in[k].
  * Evaluated as Gaussian-chirp diagonal * FFT convolution * diagonal with every
  * factor of modulus <= 1.  z = 1 and z = -1 return the continuum limits
- * sqrt(2 pi) in[j] and sqrt(2 pi) in[N-1-j].  |z| > 1 (beyond 1e-12) gives
- * LCT_ERR_DOMAIN.  Only N and the precision of the plan are used.
+ * sqrt(2 pi) in[j] and sqrt(2 pi) in[N-1-j].  |z| > 1 + 1e-12 gives
+ * LCT_ERR_DOMAIN; orders with 1 < |z| <= 1 + 1e-12 are taken on the unit
+ * circle (z / |z|).  Only N and the precision of the plan are used.
  */
 int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,
               hipStream_t stream);
@@ -195,8 +203,15 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
  * rounding) as chirp * Gaussian-chirp convolution * chirp in the Toeplitz
  * form, or, input reversed, the Hankel form, whichever has all three factors
  * of modulus <= 1; a matrix for which neither does (the sum would add and
- * cancel exponentially large terms) gives LCT_ERR_DOMAIN.  Real matrices
- * always qualify (unit-modulus chirps).  One matrix per call: its
+ * cancel exponentially large terms) gives LCT_ERR_DOMAIN.  With conj(b)
+ * written b*, the accepted domain is
+ *   Toeplitz:  Im b <= 0,  Im[(a - 1) b*] >= 0,  Im[(d - 1) b*] >= 0,   or
+ *   Hankel:    Im b >= 0,  Im[(a + 1) b*] >= 0,  Im[(d + 1) b*] >= 0
+ * (each up to a relative slack of 1e-12; the factors are i(a -+ 1)/(2b),
+ * +-i/(2b) and i(d -+ 1)/(2b), and Re(i q/(2b)) = -Im(q b*)/(2|b|^2)).  Real
+ * matrices always qualify (unit-modulus chirps); the bilateral Laplace matrix
+ * (0, i, i, 0), whose kernel e^{-x y} has no bounded splitting on a real
+ * grid, does not.  One matrix per call: its
  * convolution kernel's spectrum is computed once for the batch when a
  * workspace is given (always, for two-pass lengths).  Workspace, alignment and in != out as frft_exec_ws
  * (frft_workspace_size).  b == 0 and LCT_FP32_SPLITBF16 give
@@ -233,19 +248,54 @@ int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, 
  */
 enum { LCT_KIND_LCT = 0, LCT_KIND_FRFT = 1 };
 typedef struct {
-    int64_t offset;
-    int32_t N;
-    int32_t kind;
-    double p[4];
+    int64_t offset; /* element offset in `in` and `out` */
+    int32_t N;      /* length */
+    int32_t kind;   /* LCT_KIND_LCT or LCT_KIND_FRFT */
+    int32_t prec;   /* lct_precision; must equal the plan's (LCT_FP32) */
+    int32_t pad;    /* reserved, must be 0 */
+    double p[4];    /* (a, b, c, d) or (re z, im z, 0, 0) */
 } lct_desc;
 typedef struct lct_ragged_s *lct_ragged_plan;
 int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t nsig, lct_precision prec);
 size_t lct_ragged_workspace_size(lct_ragged_plan p);
+/*
+ * Workspace bytes lct_exec_ragged needs for these HOST descriptors (the same
+ * value lct_ragged_workspace_size returns for a plan made from them), without
+ * making a plan: 256 bytes of counter, then 2 x 2N complex64 samples per
+ * fractional transform too long for one work-group's LDS.  The descriptors are
+ * validated as by lct_ragged_plan_create (the precision is that of the first
+ * descriptor; all must agree); on error *bytes is 0 and the code is returned.
+ */
+int lct_workspace_size(const lct_desc *h_desc, int64_t nsig, size_t *bytes);
 /* Host query: number of work items, persistent grid size, dynamic LDS bytes. */
 int lct_ragged_info(lct_ragged_plan p, int *nitems, int *grid, size_t *lds_bytes);
 int lct_exec_ragged(lct_ragged_plan p, const lct_desc *d_desc, const void *in, void *out, void *ws,
                     size_t ws_bytes, hipStream_t stream);
 void lct_ragged_plan_destroy(lct_ragged_plan p);
+
+/*
+ * Device-side check of per-signal parameters that live on the device and so
+ * are not validated on the host (lct_exec_many, the adjoints and the
+ * parameter gradient: M4; frft_exec_many[_ws]: Z2; lct_exec_ragged: the
+ * descriptors).  A row is invalid when
+ *   LCT_KIND_LCT (M4 rows a, b, c, d): an entry is not finite, or
+ *     |ad - bc - 1| > 1e-10 max(1, |ad|, |bc|) (§1; this includes b = d = 0,
+ *     for which the transform divides by zero);
+ *   LCT_KIND_FRFT (Z2 rows re z, im z): a part is not finite, or
+ *     |z| > 1 + 1e-12 (the quadrature of eq. eqifft needs |z| <= 1);
+ *   descriptors: the same per kind, plus an unknown kind, N outside
+ *     [1, 2^24] or not 2^p 3^q 5^r, a negative offset, a precision other
+ *     than LCT_FP32 or pad != 0.
+ * The transforms do not check these rows: an invalid row gives NaN or
+ * meaningless output for that signal only.
+ * status: DEVICE memory of two int64: status[0] = the number of invalid rows,
+ * status[1] = the index of the first invalid row (or -1).  Both are written
+ * by one small kernel on `stream` (no memset, no host synchronisation), so
+ * the check can sit in the same stream or graph as the transform.  P and
+ * d_desc 8-byte aligned; batch/nsig >= 0 (0 writes {0, -1}).
+ */
+int lct_check_params(int kind, const double *P, int64_t batch, int64_t *status, hipStream_t stream);
+int lct_check_desc(const lct_desc *d_desc, int64_t nsig, int64_t *status, hipStream_t stream);
 
 /*
  * Autotuner.  The launch geometry of a transform (values per thread, signals

@@ -277,12 +277,13 @@ def frft_exec_many(x: torch.Tensor, Z2: torch.Tensor, out=None, stream=None, ws=
 # ---------------------------------------------------------------------------
 # Ragged batches: one persistent launch over signals of different lengths.
 # ---------------------------------------------------------------------------
-DESC_DTYPE = np.dtype([("offset", "<i8"), ("N", "<i4"), ("kind", "<i4"), ("p", "<f8", (4,))])
+DESC_DTYPE = np.dtype([("offset", "<i8"), ("N", "<i4"), ("kind", "<i4"), ("prec", "<i4"), ("pad", "<i4"),
+                       ("p", "<f8", (4,))])
 LCT_KIND_LCT = 0
 LCT_KIND_FRFT = 1
 
 
-def make_descriptors(sizes, kinds, params) -> np.ndarray:
+def make_descriptors(sizes, kinds, params, precision: int = LCT_FP32) -> np.ndarray:
     """Descriptor array (C layout lct_desc) for signals stored back to back:
     sizes[i] samples, kinds[i] in {LCT_KIND_LCT, LCT_KIND_FRFT}, params[i] =
     (a, b, c, d) or (re z, im z, 0, 0)."""
@@ -291,8 +292,47 @@ def make_descriptors(sizes, kinds, params) -> np.ndarray:
     d["offset"] = np.concatenate([[0], np.cumsum(sizes)[:-1]]) if sizes.size else []
     d["N"] = sizes
     d["kind"] = np.asarray(kinds, dtype=np.int32)
+    d["prec"] = int(precision)
     d["p"] = np.asarray(params, dtype=np.float64).reshape(-1, 4)
     return d
+
+
+def lct_workspace_size(desc: np.ndarray) -> int:
+    """Workspace bytes of lct_exec_ragged for these (host) descriptors."""
+    desc = np.ascontiguousarray(desc, dtype=DESC_DTYPE)
+    n = ctypes.c_size_t()
+    _lib.check(_lib.load().lct_workspace_size(desc.ctypes.data if desc.size else None, desc.shape[0],
+                                              ctypes.byref(n)), "lct_workspace_size")
+    return int(n.value)
+
+
+def lct_check_params(P: torch.Tensor, kind: int = None, status=None, stream=None) -> torch.Tensor:
+    """Device-side check of per-signal parameters: P is a (batch, 4) float64 tensor
+    of matrices (kind LCT_KIND_LCT) or (batch, 2) of orders (LCT_KIND_FRFT).
+    Returns a device int64 tensor {number of invalid rows, first invalid row or -1}."""
+    if P.dtype != torch.float64 or not P.is_contiguous() or P.dim() != 2 or P.shape[1] not in (2, 4):
+        raise ValueError("P must be a contiguous (batch, 4) or (batch, 2) float64 tensor")
+    if kind is None:
+        kind = LCT_KIND_LCT if P.shape[1] == 4 else LCT_KIND_FRFT
+    if P.shape[1] != (4 if kind == LCT_KIND_LCT else 2):
+        raise ValueError("row width does not match the kind")
+    if status is None:
+        status = torch.empty(2, dtype=torch.int64, device=P.device)
+    rc = _lib.load().lct_check_params(int(kind), P.data_ptr(), P.shape[0], status.data_ptr(), _stream_handle(stream))
+    _lib.check(rc, "lct_check_params")
+    return status
+
+
+def lct_check_desc(d_desc: torch.Tensor, nsig: int, status=None, stream=None) -> torch.Tensor:
+    """Device-side check of ragged descriptors held on the device (uint8 tensor of
+    nsig lct_desc records).  Returns {number of invalid descriptors, first or -1}."""
+    if d_desc.dtype != torch.uint8 or d_desc.numel() != nsig * DESC_DTYPE.itemsize:
+        raise ValueError("d_desc must hold nsig lct_desc records as uint8")
+    if status is None:
+        status = torch.empty(2, dtype=torch.int64, device=d_desc.device)
+    rc = _lib.load().lct_check_desc(d_desc.data_ptr(), int(nsig), status.data_ptr(), _stream_handle(stream))
+    _lib.check(rc, "lct_check_desc")
+    return status
 
 
 class RaggedPlan:

@@ -65,6 +65,9 @@ SIGNATURES = {
     "lct_ragged_info": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_size_t)]),
     "lct_exec_ragged": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "lct_ragged_plan_destroy": (None, [_vp]),
+    "lct_workspace_size": (_int, [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "lct_check_params": (_int, [_int, _vp, _i64, _vp, _vp]),
+    "lct_check_desc": (_int, [_vp, _i64, _vp, _vp]),
     "lct_autotune": (_int, [_i64, _int, _int, _i64, _vp, _vp]),
     "lct_tune_candidates": (_int, [_i64, _int, _int, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_int)]),
     "lct_tune_get": (_int, [_i64, _int, _int, ctypes.c_char_p, ctypes.c_size_t]),

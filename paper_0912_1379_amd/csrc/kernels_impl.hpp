@@ -230,11 +230,37 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct(
 }
 
 // ---------------------------------------------------------------------------
-// Parameter gradient (b != 0): G = L f and H = L(i x_k^2/(2b) f) in LDS, then
+// Parameter gradient.  b != 0: G = L f and H = L(i x_k^2/(2b) f) in LDS, then
 // per-signal sums  S_H = Re sum conj(g) H,  S_G = Re sum conj(g) G,
 // S_n = Re sum conj(g) i (n_j^2 / N) G, combined into
 // dl/da = S_H, dl/db = -S_G/(2b) - (a/b) S_H + d S_n, dl/dc = 0, dl/dd = b S_n.
+// b = 0 (the diagonal of §1, G_j = sqrt(d) e^{i c x_j^2/(2d)} f_j, output
+// nodes x_j/d): dG_j/dc = i x_j^2/(2d) G_j and dG_j/dd = (1/(2d) - i c x_j^2/(2d^2)) G_j,
+// so with x_j^2 = pi^2 n_j^2/(8N) the same S_G and S_n give
+// dl/dc = pi^2 S_n / (16 d), dl/dd = S_G/(2d) - (c/d) dl/dc, dl/da = dl/db = 0.
+// Such a signal joins the work-group's FFTs (their barriers are uniform) and
+// ignores their results.
+// The sums are reduced in a fixed order (a tree over the slot's threads in
+// LDS), so the gradient is the same bit for bit on every run.
 // ---------------------------------------------------------------------------
+// Sum of one value per thread of a signal slot (T threads, buf holds at least T
+// doubles of the slot's own LDS); every thread of the work-group calls it.
+__device__ __forceinline__ double slot_sum(double v, double *buf, int t, int T)
+{
+    __syncthreads();
+    buf[t] = v;
+    __syncthreads();
+    int w = 1;
+    while (w < T)
+        w <<= 1;
+    for (w >>= 1; w >= 1; w >>= 1) {
+        if (t < w && t + w < T)
+            buf[t] += buf[t + w];
+        __syncthreads();
+    }
+    return buf[0];
+}
+
 template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 __global__ __launch_bounds__(LB) void k_lct_pgrad(
     const typename Vec<R>::T *__restrict__ f, const typename Vec<R>::T *__restrict__ g,
@@ -251,29 +277,23 @@ __global__ __launch_bounds__(LB) void k_lct_pgrad(
     const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
     const bool live = sig < args.batch;
     C<R> *lds = smem + (size_t)sl * lds_elems(N);
-    // three FP64 accumulators per signal slot after the FFT area
-    double *acc = reinterpret_cast<double *>(smem + (size_t)args.S * lds_elems(N)) + 3 * sl;
     const double inv2N = 0.5 / (double)N;
     const int64_t ss = live ? sig : 0;
-    const double a = args.M4[4 * ss + 0], b = args.M4[4 * ss + 1], d = args.M4[4 * ss + 3];
-    const LctConst k = lct_const_from(args.nc, a, b, args.M4[4 * ss + 2], d);
+    const double a = args.M4[4 * ss + 0], b = args.M4[4 * ss + 1], c = args.M4[4 * ss + 2],
+                 d = args.M4[4 * ss + 3];
+    const LctConst k = lct_const_from(args.nc, a, b, c, d);
     const V *fs = f + (size_t)ss * N;
     const V *gs = g + (size_t)ss * N;
-    if (t == 0) {
-        acc[0] = 0.0;
-        acc[1] = 0.0;
-        acc[2] = 0.0;
-    }
 
     // x_k^2 / (2b) = pi^2 n_k^2 / (16 b N)
-    const double qscale = PI_HI * PI_HI / (16.0 * b * (double)N);
+    const double qscale = k.b0 ? 0.0 : PI_HI * PI_HI / (16.0 * b * (double)N);
     double sH = 0.0, sG = 0.0, sN = 0.0;
     C<R> v[E];
     for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = t + T * e;
-            C<R> x = live ? ldc<R>(fs + i) : C<R>{(R)0, (R)0};
+            C<R> x = live && !k.b0 ? ldc<R>(fs + i) : C<R>{(R)0, (R)0};
             x = cmul(x, pre_factor<R>(k, i, N, inv2N));
             if (pass == 0)
                 x = cmul_pi(cscale(x, (R)(qscale * nsq(i, N))));
@@ -286,9 +306,16 @@ __global__ __launch_bounds__(LB) void k_lct_pgrad(
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = t + T * e;
-            if (!live)
+            if (!live || (k.b0 && pass == 0))
                 continue;
-            C<R> y = cmul(v[e], post_factor<R>(k, j, N, inv2N));
+            C<R> y;
+            if (k.b0) {
+                // the diagonal: sqrt(d) e^{i c x_j^2/(2d)} f_j
+                const double tj = quad_turns(Quad{k.post_hi, k.post_lo}, nsq(j, N)) + k.amp_turns;
+                y = cmul(ldc<R>(fs + j), cscale(cis_turns_from<R>(frac_turns(tj)), (R)k.amp_mag));
+            } else {
+                y = cmul(v[e], post_factor<R>(k, j, N, inv2N));
+            }
             C<R> gj = ldc<R>(gs + j);
             // Re(conj(g) y)
             double re = (double)gj.x * (double)y.x + (double)gj.y * (double)y.y;
@@ -302,24 +329,24 @@ __global__ __launch_bounds__(LB) void k_lct_pgrad(
             }
         }
     }
-    __syncthreads();
-    if (live) {
-        atomicAdd(&acc[0], sH);
-        atomicAdd(&acc[1], sG);
-        atomicAdd(&acc[2], sN);
-    }
-    __syncthreads();
-    if (live && t == 0 && b == 0.0) {
-        // the diagonal b = 0 branch of §1 is not differentiated here
-        grad4[4 * sig + 0] = 0.0;
-        grad4[4 * sig + 1] = 0.0;
-        grad4[4 * sig + 2] = 0.0;
-        grad4[4 * sig + 3] = 0.0;
-    } else if (live && t == 0) {
-        grad4[4 * sig + 0] = acc[0];
-        grad4[4 * sig + 1] = -acc[1] / (2.0 * b) - (a / b) * acc[0] + d * acc[2];
-        grad4[4 * sig + 2] = 0.0;
-        grad4[4 * sig + 3] = b * acc[2];
+    // the slot's FFT area (at least N complex values) holds the T partial sums
+    double *buf = reinterpret_cast<double *>(lds);
+    const double SH = slot_sum(sH, buf, t, T);
+    const double SG = slot_sum(sG, buf, t, T);
+    const double SN = slot_sum(sN, buf, t, T);
+    if (live && t == 0) {
+        if (k.b0) {
+            const double gc = PI_HI * PI_HI * SN / (16.0 * d);
+            grad4[4 * sig + 0] = 0.0;
+            grad4[4 * sig + 1] = 0.0;
+            grad4[4 * sig + 2] = gc;
+            grad4[4 * sig + 3] = SG / (2.0 * d) - (c / d) * gc;
+        } else {
+            grad4[4 * sig + 0] = SH;
+            grad4[4 * sig + 1] = -SG / (2.0 * b) - (a / b) * SH + d * SN;
+            grad4[4 * sig + 2] = 0.0;
+            grad4[4 * sig + 3] = b * SN;
+        }
     }
 }
 

@@ -43,12 +43,19 @@ int check_ptr(const void *p, bool fp64)
 
 int validate_M(double a, double b, double c, double d)
 {
-    if (!isfinite(a) || !isfinite(b) || !isfinite(c) || !isfinite(d))
+    if (!lct_row_finite(a, b, c, d))
         return LCT_ERR_ARG;
-    double ad = a * d, bc = b * c;
-    double tol = 1e-10 * fmax(1.0, fmax(fabs(ad), fabs(bc)));
-    if (fabs(ad - bc - 1.0) > tol)
+    if (!lct_row_unimodular(a, b, c, d))
         return LCT_ERR_NOT_UNIMODULAR;
+    return LCT_OK;
+}
+
+int validate_z(double z_re, double z_im)
+{
+    if (!frft_row_finite(z_re, z_im))
+        return LCT_ERR_ARG;
+    if (!frft_row_in_disc(z_re, z_im))
+        return LCT_ERR_DOMAIN;
     return LCT_OK;
 }
 
@@ -135,42 +142,36 @@ size_t frft_ws_bytes(int64_t N, bool fp64, int64_t batch)
 // neither gives LCT_ERR_DOMAIN.
 int same_grid_const(int64_t N, double ar, double ai, double br, double bi, double dr, double di, FrConst *k)
 {
-    double wr, wi; // i / (2b)
-    cdiv(0.0, 1.0, 2.0 * br, 2.0 * bi, wr, wi);
-    auto mulw = [&](double xr, double xi, double &pr, double &pi_) {
-        pr = wr * xr - wi * xi;
-        pi_ = wr * xi + wi * xr;
-    };
-    auto bounded = [](double re, double im) { return re <= 1e-12 * fmax(1.0, fabs(im)); };
-    double tir, tii, tor, toi, hir, hii, hor, hoi;
-    mulw(ar - 1.0, ai, tir, tii);
-    mulw(dr - 1.0, di, tor, toi);
-    mulw(ar + 1.0, ai, hir, hii);
-    mulw(dr + 1.0, di, hor, hoi);
-    const bool toep = bounded(tir, tii) && bounded(wr, wi) && bounded(tor, toi);
-    const bool hank = bounded(hir, hii) && bounded(-wr, -wi) && bounded(hor, hoi);
+    // w = i / (2b) and the factors in double-double: their imaginary parts
+    // become phase rates per n^2
+    const CDD w = cdd_div(cdd_of(0.0, 1.0), cdd_of(2.0 * br, 2.0 * bi));
+    auto mulw = [&](double xr, double sgn, double xi) { return cdd_mul(w, CDD{dd_two_sum(xr, sgn), DD{xi, 0.0}}); };
+    auto bounded = [](const CDD &x) { return x.re.hi <= 1e-12 * fmax(1.0, fabs(x.im.hi)); };
+    const CDD ti = mulw(ar, -1.0, ai), to = mulw(dr, -1.0, di);
+    const CDD hi = mulw(ar, 1.0, ai), ho = mulw(dr, 1.0, di);
+    const CDD wn{dd_neg(w.re), dd_neg(w.im)};
+    const bool toep = bounded(ti) && bounded(w) && bounded(to);
+    const bool hank = bounded(hi) && bounded(wn) && bounded(ho);
     if (!toep && !hank)
         return LCT_ERR_DOMAIN;
     *k = FrConst{};
     k->special = 0;
     k->hankel = toep ? 0 : 1;
-    const double inr = toep ? tir : hir, ini = toep ? tii : hii;
-    const double our = toep ? tor : hor, oui = toep ? toi : hoi;
-    const double kr = toep ? wr : -wr, ki = toep ? wi : -wi;
+    const CDD in = toep ? ti : hi, ou = toep ? to : ho, kk = toep ? w : wn;
     const double n = (double)N;
     const DD pi{PI_HI, PI_LO};
     // x^2 = pi^2 n^2 / (8N): log-modulus Re(.) pi^2 / (8N), turns Im(.) pi / (16N) per n^2
-    k->dmag = inr * PI_HI * PI_HI / (8.0 * n);
-    DD t = dd_div_d(dd_mul_d(pi, ini), 16.0 * n);
+    k->dmag = in.re.hi * PI_HI * PI_HI / (8.0 * n);
+    DD t = dd_div_d(dd_mul(pi, in.im), 16.0 * n);
     k->dph_hi = t.hi;
     k->dph_lo = t.lo;
-    k->omag = our * PI_HI * PI_HI / (8.0 * n);
-    t = dd_div_d(dd_mul_d(pi, oui), 16.0 * n);
+    k->omag = ou.re.hi * PI_HI * PI_HI / (8.0 * n);
+    t = dd_div_d(dd_mul(pi, ou.im), 16.0 * n);
     k->oph_hi = t.hi;
     k->oph_lo = t.lo;
     // h^2 m^2 = pi^2 m^2 / (2N): log-modulus Re pi^2 / (2N), turns Im pi / (4N) per m^2
-    k->kmag = kr * PI_HI * PI_HI / (2.0 * n);
-    t = dd_div_d(dd_mul_d(pi, ki), 4.0 * n);
+    k->kmag = kk.re.hi * PI_HI * PI_HI / (2.0 * n);
+    t = dd_div_d(dd_mul(pi, kk.im), 4.0 * n);
     k->kph_hi = t.hi;
     k->kph_lo = t.lo;
     // h (2 pi i b)^(-1/2) / (2N), principal root; 2 pi i b = -2 pi b_im + i 2 pi b_re
@@ -473,7 +474,7 @@ int lct_param_grad_many(int64_t N, lct_precision prec, const double *M4, const v
         return LCT_ERR_ARG;
     if (N > lct_max_single_pass(prec))
         return LCT_ERR_UNSUPPORTED;
-    const Tiling tl = default_tiling(N, fp64, false, 3 * sizeof(double));
+    const Tiling tl = default_tiling(N, fp64, false, 0);
     if (!tl.ok)
         return LCT_ERR_UNSUPPORTED;
     LctArgs a{};
@@ -499,10 +500,8 @@ int frft_exec(lct_plan p, double z_re, double z_im, const void *in, void *out, i
         return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
     if (p->s != 1.0)
         return LCT_ERR_UNSUPPORTED; // the same-grid fractional transform is defined on x_k only
-    if (!isfinite(z_re) || !isfinite(z_im))
-        return LCT_ERR_ARG;
-    if (hypot(z_re, z_im) > 1.0 + 1e-12)
-        return LCT_ERR_DOMAIN;
+    if (int rc = validate_z(z_re, z_im))
+        return rc;
     FrConst k = fr_const(p->N, z_re, z_im);
     return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, nullptr, 0, stream);
 }
@@ -516,10 +515,8 @@ int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out
         return LCT_ERR_UNSUPPORTED; // the fractional transform has no matrix-core variant
     if (p->s != 1.0)
         return LCT_ERR_UNSUPPORTED; // the same-grid fractional transform is defined on x_k only
-    if (!isfinite(z_re) || !isfinite(z_im))
-        return LCT_ERR_ARG;
-    if (hypot(z_re, z_im) > 1.0 + 1e-12)
-        return LCT_ERR_DOMAIN;
+    if (int rc = validate_z(z_re, z_im))
+        return rc;
     FrConst k = fr_const(p->N, z_re, z_im);
     return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, ws_bytes, stream);
 }

@@ -50,6 +50,52 @@ __host__ __device__ inline DD dd_div_d(DD x, double d)
     return dd_quick(q1, rem / d);
 }
 
+__host__ __device__ inline DD dd_two_sum(double a, double b)
+{
+#pragma clang fp contract(off)
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__host__ __device__ inline DD dd_add(DD x, DD y)
+{
+#pragma clang fp contract(off)
+    DD s = dd_two_sum(x.hi, y.hi);
+    return dd_quick(s.hi, s.lo + x.lo + y.lo);
+}
+__host__ __device__ inline DD dd_neg(DD x) { return {-x.hi, -x.lo}; }
+__host__ __device__ inline DD dd_sub(DD x, DD y) { return dd_add(x, dd_neg(y)); }
+__host__ __device__ inline DD dd_div(DD x, DD y)
+{
+#pragma clang fp contract(off)
+    double q1 = x.hi / y.hi;
+    DD r = dd_sub(x, dd_mul_d(y, q1));
+    double q2 = r.hi / y.hi;
+    return dd_quick(q1, q2);
+}
+
+// Complex double-double: the fractional and complex-matrix constants whose
+// imaginary parts become phase coefficients per n^2 (up to 2^48 at the largest
+// lengths) are formed in it, so that their rounding stays below the FP64
+// transform's error.
+struct CDD {
+    DD re, im;
+};
+__host__ __device__ inline CDD cdd_mul(CDD a, CDD b)
+{
+    return {dd_sub(dd_mul(a.re, b.re), dd_mul(a.im, b.im)), dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re))};
+}
+__host__ __device__ inline CDD cdd_div(CDD a, CDD b)
+{
+    // a conj(b) / |b|^2, scaled by the larger part of b so that |b|^2 cannot overflow
+    const double sc = fmax(fabs(b.re.hi), fabs(b.im.hi));
+    const CDD bs{dd_div_d(b.re, sc), dd_div_d(b.im, sc)};
+    const DD den = dd_add(dd_mul(bs.re, bs.re), dd_mul(bs.im, bs.im));
+    const CDD num = cdd_mul(a, CDD{bs.re, dd_neg(bs.im)});
+    return {dd_div_d(dd_div(num.re, den), sc), dd_div_d(dd_div(num.im, den), sc)};
+}
+__host__ __device__ inline CDD cdd_of(double re, double im) { return {DD{re, 0.0}, DD{im, 0.0}}; }
+
 // pi and 1/(2 pi) as unevaluated double-double sums
 constexpr double PI_HI = 3.141592653589793;
 constexpr double PI_LO = 1.2246467991473532e-16;
@@ -193,6 +239,24 @@ __host__ __device__ inline LctConst lct_const_from(const NConst &nc, double a, d
     return k;
 }
 
+// Validity of one signal's parameters (shared by the host checks and the
+// device-side status check).
+//   matrix (a, b, c, d): finite, and ad - bc = 1 (§1) within
+//     |ad - bc - 1| <= 1e-10 max(1, |ad|, |bc|)  (this also excludes b = d = 0);
+//   fractional order z: finite and |z| <= 1 + 1e-12 (eq. eqifft needs |z| <= 1;
+//     the slack above 1 is projected onto the unit circle by fr_const).
+__host__ __device__ inline bool lct_row_finite(double a, double b, double c, double d)
+{
+    return isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d);
+}
+__host__ __device__ inline bool lct_row_unimodular(double a, double b, double c, double d)
+{
+    const double ad = a * d, bc = b * c;
+    return fabs(ad - bc - 1.0) <= 1e-10 * fmax(1.0, fmax(fabs(ad), fabs(bc)));
+}
+__host__ __device__ inline bool frft_row_finite(double zr, double zi) { return isfinite(zr) && isfinite(zi); }
+__host__ __device__ inline bool frft_row_in_disc(double zr, double zi) { return hypot(zr, zi) <= 1.0 + 1e-12; }
+
 // Per-signal constants of the same-grid fractional transform (eq. fasy with
 // y_j = x_j).  Writing the exponent as
 //   -P (x_j^2 + x_k^2) - beta (x_j -+ x_k)^2
@@ -251,6 +315,13 @@ __host__ __device__ inline void csqrt_principal(double re, double im, double &sr
 __host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
 {
     FrConst k{};
+    // orders accepted just outside the unit circle (|z| <= 1 + 1e-12) are
+    // taken on it, where every factor still has modulus <= 1
+    const double rz = hypot(zr, zi);
+    if (rz > 1.0) {
+        zr /= rz;
+        zi /= rz;
+    }
     if (zi == 0.0 && (zr == 1.0 || zr == -1.0)) {
         k.special = zr > 0 ? 1 : 2;
         k.cre = sqrt(2.0 * PI_HI);
@@ -260,25 +331,27 @@ __host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
     k.hankel = zr < 0.0 ? 1 : 0;
     double s = k.hankel ? -1.0 : 1.0; // z -> s z maps the Hankel case onto the Toeplitz formulas
     double wr = s * zr, wi = s * zi;
-    // P = (1 - w) / (2 (1 + w)), beta = w / (1 - w^2)  (w^2 = z^2)
-    double Pr, Pi;
-    cdiv(1.0 - wr, -wi, 2.0 * (1.0 + wr), 2.0 * wi, Pr, Pi);
-    double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
-    double omr = 1.0 - z2r, omi = -z2i;
-    double Br, Bi;
-    cdiv(wr, wi, omr, omi, Br, Bi);
+    // P = (1 - w) / (2 (1 + w)), beta = w / (1 - w^2)  (w^2 = z^2), in
+    // double-double: their imaginary parts are phase rates per n^2 and m^2
+    const CDD P = cdd_div(CDD{dd_two_sum(1.0, -wr), DD{-wi, 0.0}},
+                          CDD{dd_mul_d(dd_two_sum(1.0, wr), 2.0), DD{2.0 * wi, 0.0}});
+    const CDD z2{dd_sub(dd_two_prod(zr, zr), dd_two_prod(zi, zi)), dd_mul_d(dd_two_prod(zr, zi), 2.0)};
+    const CDD om{dd_sub(DD{1.0, 0.0}, z2.re), dd_neg(z2.im)};
+    const CDD B = cdd_div(cdd_of(wr, wi), om);
     const double n = (double)N;
+    const DD pi{PI_HI, PI_LO};
     // exp(-P x^2), x^2 = pi^2 n^2 / (8N)
-    k.dmag = -Pr * PI_HI * PI_HI / (8.0 * n);
-    DD dph = dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, -Pi), 16.0 * n); // -Im P pi^2/(8N) / (2 pi)
+    k.dmag = -P.re.hi * PI_HI * PI_HI / (8.0 * n);
+    DD dph = dd_div_d(dd_mul(pi, dd_neg(P.im)), 16.0 * n); // -Im P pi^2/(8N) / (2 pi)
     k.dph_hi = dph.hi;
     k.dph_lo = dph.lo;
     // exp(-beta h^2 m^2), h^2 = pi^2 / (2N)
-    k.kmag = -Br * PI_HI * PI_HI / (2.0 * n);
-    DD kph = dd_div_d(dd_mul_d(DD{PI_HI, PI_LO}, -Bi), 4.0 * n); // -Im beta pi^2/(2N) / (2 pi)
+    k.kmag = -B.re.hi * PI_HI * PI_HI / (2.0 * n);
+    DD kph = dd_div_d(dd_mul(pi, dd_neg(B.im)), 4.0 * n); // -Im beta pi^2/(2N) / (2 pi)
     k.kph_hi = kph.hi;
     k.kph_lo = kph.lo;
     // h sqrt(2 / (1 - z^2)) / (2N)
+    const double omr = om.re.hi + om.re.lo, omi = om.im.hi + om.im.lo;
     double qr, qi;
     cdiv(2.0, 0.0, omr, omi, qr, qi);
     double sr, si;

@@ -162,6 +162,73 @@ double item_cost(const RagSize &z, int kind, int count)
     }
 }
 
+// Validates the host descriptors and classifies every signal: its size class
+// (one per (kind, N)), its item kind (a single-pass group or a four-step item)
+// and, for long fractional transforms, its offset (complex samples) in the
+// workspace after the counter.  Shared by the plan and lct_workspace_size.
+int classify(const lct_desc *h_desc, int64_t nsig, int prec, std::vector<RagSize> &sizes, std::vector<int> &size_of,
+             std::vector<int> &kind_of, std::vector<int64_t> &wsoff, int64_t &ws_elems)
+{
+    struct Key {
+        int kind;
+        int N;
+    };
+    std::vector<Key> keys;
+    ws_elems = 0;
+    for (int64_t s = 0; s < nsig; ++s) {
+        const lct_desc &d = h_desc[s];
+        if (d.prec != prec || d.pad != 0)
+            return LCT_ERR_ARG;
+        if (d.offset < 0 || !smooth235r(d.N) || d.N > (1 << 24))
+            return LCT_ERR_UNSUPPORTED_N;
+        if (d.kind == LCT_KIND_LCT) {
+            if (!lct_row_finite(d.p[0], d.p[1], d.p[2], d.p[3]))
+                return LCT_ERR_ARG;
+            if (!lct_row_unimodular(d.p[0], d.p[1], d.p[2], d.p[3]))
+                return LCT_ERR_NOT_UNIMODULAR;
+        } else if (d.kind == LCT_KIND_FRFT) {
+            if (!frft_row_finite(d.p[0], d.p[1]))
+                return LCT_ERR_ARG;
+            if (!frft_row_in_disc(d.p[0], d.p[1]))
+                return LCT_ERR_DOMAIN;
+        } else {
+            return LCT_ERR_ARG;
+        }
+        int idx = -1;
+        for (size_t q = 0; q < keys.size(); ++q)
+            if (keys[q].kind == d.kind && keys[q].N == d.N)
+                idx = (int)q;
+        if (idx < 0) {
+            RagSize z{};
+            z.N = d.N;
+            z.nc = n_const_host(d.N);
+            const int64_t L = d.kind == LCT_KIND_LCT ? d.N : 2 * (int64_t)d.N;
+            if (!rag_group(L, z)) {
+                z.E = z.T = z.S = 0; // not a single-pass group: two-pass item
+                if (!rag_split(L, z))
+                    return LCT_ERR_UNSUPPORTED;
+            }
+            sizes.push_back(z);
+            keys.push_back({d.kind, d.N});
+            idx = (int)sizes.size() - 1;
+        }
+        size_of[s] = idx;
+        const RagSize &z = sizes[idx];
+        const bool group = z.E != 0;
+        kind_of[s] = d.kind == LCT_KIND_LCT ? (group ? RI_LCT_GROUP : RI_LCT_BIG)
+                                            : (group ? RI_FRFT_GROUP : RI_FRFT_BIG);
+        if (kind_of[s] == RI_FRFT_BIG) {
+            wsoff[s] = ws_elems;
+            ws_elems += 2 * 2 * (int64_t)d.N;
+        }
+    }
+    return LCT_OK;
+}
+
+// Workspace bytes: the 256-byte counter block, then 2 x 2N complex64 samples
+// per long fractional transform.
+size_t ws_bytes_of(int64_t ws_elems) { return 256 + (size_t)ws_elems * 8; }
+
 template <typename T> int upload(T **dst, const std::vector<T> &v)
 {
     *dst = nullptr;
@@ -203,63 +270,12 @@ int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t
     if (prec != LCT_FP32)
         return (prec == LCT_FP64 || prec == LCT_FP32_SPLITBF16) ? LCT_ERR_UNSUPPORTED : LCT_ERR_ARG;
 
-    // validate and classify
-    struct Key {
-        int kind;
-        int N;
-    };
     std::vector<RagSize> sizes;
-    std::vector<Key> keys;
     std::vector<int> size_of(nsig), kind_of(nsig);
     std::vector<int64_t> wsoff(nsig, 0);
     int64_t ws_elems = 0;
-    for (int64_t s = 0; s < nsig; ++s) {
-        const lct_desc &d = h_desc[s];
-        if (d.offset < 0 || !smooth235r(d.N) || d.N > (1 << 24))
-            return LCT_ERR_UNSUPPORTED_N;
-        if (d.kind == LCT_KIND_LCT) {
-            for (int q = 0; q < 4; ++q)
-                if (!isfinite(d.p[q]))
-                    return LCT_ERR_ARG;
-            const double ad = d.p[0] * d.p[3], bc = d.p[1] * d.p[2];
-            if (fabs(ad - bc - 1.0) > 1e-10 * fmax(1.0, fmax(fabs(ad), fabs(bc))))
-                return LCT_ERR_NOT_UNIMODULAR;
-        } else if (d.kind == LCT_KIND_FRFT) {
-            if (!isfinite(d.p[0]) || !isfinite(d.p[1]))
-                return LCT_ERR_ARG;
-            if (hypot(d.p[0], d.p[1]) > 1.0 + 1e-12)
-                return LCT_ERR_DOMAIN;
-        } else {
-            return LCT_ERR_ARG;
-        }
-        int idx = -1;
-        for (size_t q = 0; q < keys.size(); ++q)
-            if (keys[q].kind == d.kind && keys[q].N == d.N)
-                idx = (int)q;
-        if (idx < 0) {
-            RagSize z{};
-            z.N = d.N;
-            z.nc = n_const_host(d.N);
-            const int64_t L = d.kind == LCT_KIND_LCT ? d.N : 2 * (int64_t)d.N;
-            if (!rag_group(L, z)) {
-                z.E = z.T = z.S = 0; // not a single-pass group: two-pass item
-                if (!rag_split(L, z))
-                    return LCT_ERR_UNSUPPORTED;
-            }
-            sizes.push_back(z);
-            keys.push_back({d.kind, d.N});
-            idx = (int)sizes.size() - 1;
-        }
-        size_of[s] = idx;
-        const RagSize &z = sizes[idx];
-        const bool group = z.E != 0;
-        kind_of[s] = d.kind == LCT_KIND_LCT ? (group ? RI_LCT_GROUP : RI_LCT_BIG)
-                                            : (group ? RI_FRFT_GROUP : RI_FRFT_BIG);
-        if (kind_of[s] == RI_FRFT_BIG) {
-            wsoff[s] = ws_elems;
-            ws_elems += 2 * 2 * (int64_t)d.N;
-        }
-    }
+    if (int rc = classify(h_desc, nsig, prec, sizes, size_of, kind_of, wsoff, ws_elems))
+        return rc;
 
     // items: groups of up to S signals of one (kind, N) in descriptor order,
     // one item per two-pass signal; then LPT order
@@ -305,7 +321,7 @@ int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t
     p->nsig = nsig;
     p->nitems = (int)sorted.size();
     p->lds = lds;
-    p->ws_bytes = 256 + (size_t)ws_elems * 8;
+    p->ws_bytes = ws_bytes_of(ws_elems);
     int rc;
     if ((rc = upload(&p->d_items, sorted)) || (rc = upload(&p->d_sizes, sizes)) || (rc = upload(&p->d_sig, sig)) ||
         (rc = upload(&p->d_wsoff, wsoff))) {
@@ -334,6 +350,26 @@ int lct_ragged_plan_create(lct_ragged_plan *out, const lct_desc *h_desc, int64_t
 }
 
 size_t lct_ragged_workspace_size(lct_ragged_plan p) { return p ? p->ws_bytes : 0; }
+
+int lct_workspace_size(const lct_desc *h_desc, int64_t nsig, size_t *bytes)
+{
+    if (bytes == nullptr)
+        return LCT_ERR_ARG;
+    *bytes = 0;
+    if (nsig < 0 || nsig > INT32_MAX || (nsig > 0 && h_desc == nullptr))
+        return LCT_ERR_ARG;
+    const int prec = nsig > 0 ? h_desc[0].prec : LCT_FP32;
+    if (prec != LCT_FP32)
+        return (prec == LCT_FP64 || prec == LCT_FP32_SPLITBF16) ? LCT_ERR_UNSUPPORTED : LCT_ERR_ARG;
+    std::vector<RagSize> sizes;
+    std::vector<int> size_of(nsig), kind_of(nsig);
+    std::vector<int64_t> wsoff(nsig, 0);
+    int64_t ws_elems = 0;
+    if (int rc = classify(h_desc, nsig, prec, sizes, size_of, kind_of, wsoff, ws_elems))
+        return rc;
+    *bytes = ws_bytes_of(ws_elems);
+    return LCT_OK;
+}
 
 int lct_ragged_info(lct_ragged_plan p, int *nitems, int *grid, size_t *lds_bytes)
 {

@@ -32,6 +32,8 @@ struct RagDesc {
     int64_t offset;
     int32_t N;
     int32_t kind;
+    int32_t prec;
+    int32_t pad;
     double p[4];
 };
 

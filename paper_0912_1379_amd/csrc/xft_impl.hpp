@@ -378,25 +378,6 @@ __global__ __launch_bounds__(XTHREADS, 2) void k_xft_gemm_sb(const float *__rest
     }
 }
 
-// Complex double-double helpers for the powers of z.
-__device__ __forceinline__ DD xdd_add(DD a, DD b)
-{
-#pragma clang fp contract(off)
-    const double s = a.hi + b.hi;
-    const double bb = s - a.hi;
-    const double e = (a.hi - (s - bb)) + (b.hi - bb) + a.lo + b.lo;
-    return dd_quick(s, e);
-}
-__device__ __forceinline__ DD xdd_neg(DD a) { return DD{-a.hi, -a.lo}; }
-struct CDD {
-    DD re, im;
-};
-__device__ __forceinline__ CDD xcdd_mul(const CDD &x, const CDD &y)
-{
-    return CDD{xdd_add(dd_mul(x.re, y.re), xdd_neg(dd_mul(x.im, y.im))),
-               xdd_add(dd_mul(x.re, y.im), dd_mul(x.im, y.re))};
-}
-
 // w[n] = sqrt(2 pi) z^n, n < N, by binary powering in double-double (about
 // 2 log2(n) products, each with relative error near 2^-104), rounded once.
 template <typename R>
@@ -409,9 +390,9 @@ __global__ void k_xft_weights(double zr, double zi, int N, R *__restrict__ w)
     CDD base{DD{zr, 0.0}, DD{zi, 0.0}};
     for (int e = n; e > 0; e >>= 1) {
         if (e & 1)
-            acc = xcdd_mul(acc, base);
+            acc = cdd_mul(acc, base);
         if (e > 1)
-            base = xcdd_mul(base, base);
+            base = cdd_mul(base, base);
     }
     const DD s2pi{2.5066282746310007, -1.8328579980459167e-16}; // sqrt(2 pi), double-double
     const DD wr = dd_mul(acc.re, s2pi), wi = dd_mul(acc.im, s2pi);

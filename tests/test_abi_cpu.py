@@ -301,3 +301,119 @@ def test_tune_argument_errors(lib):
     assert lib.lct_tune_set(None) == _lib.LCT_ERR_ARG
     assert lib.lct_autotune(4096, 0, 7, 0, None, None) == _lib.LCT_ERR_ARG
     assert lib.lct_autotune(4097, 0, 0, 0, None, None) == _lib.LCT_ERR_UNSUPPORTED_N
+
+
+def _descs(rows):
+    """rows: (N, kind, p4) -> lct_desc records (host), signals back to back, FP32."""
+    import paper_0912_1379_amd as lct
+    sizes = [r[0] for r in rows]
+    return lct.make_descriptors(np.array(sizes), np.array([r[1] for r in rows]), np.array([r[2] for r in rows]))
+
+
+def _ws(lib, desc):
+    n = ctypes.c_size_t(123)
+    rc = lib.lct_workspace_size(desc.ctypes.data if desc.size else None, desc.shape[0], ctypes.byref(n))
+    return rc, n.value
+
+
+def test_descriptor_layout_matches_header():
+    """lct_desc as the binding lays it out: offset, N, kind, prec, pad, p[4] (56 bytes)."""
+    import paper_0912_1379_amd as lct
+    dt = lct.DESC_DTYPE
+    assert dt.itemsize == 56
+    assert [dt.fields[f][1] for f in ("offset", "N", "kind", "prec", "pad", "p")] == [0, 8, 12, 16, 20, 24]
+    src = re.sub(r"/\*.*?\*/", "", open(_lib.HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} lct_desc;", src).group(1)
+    assert re.findall(r"(\w+)\s*(?:\[\d+\])?;", body) == ["offset", "N", "kind", "prec", "pad", "p"]
+
+
+def test_workspace_size_from_host_descriptors(lib):
+    """Workspace of the ragged launch for host descriptors (Algorithm; the fractional
+    transform's length-2N convolution, eqs. fasy, cuadtrfor): the counter block plus
+    2 x 2N complex64 samples per fractional transform too long for one work-group."""
+    L = 0  # LCT
+    F = 1  # fractional transform
+    lctp = [1.0, 2.0, 0.5, 2.0]
+    zp = [0.5, -0.3, 0.0, 0.0]
+    assert _ws(lib, _descs([])) == (0, 256)
+    assert _ws(lib, _descs([(4096, L, lctp), (1 << 20, L, lctp), (256, F, zp)])) == (0, 256)
+    assert _ws(lib, _descs([(65536, F, zp), (256, F, zp), (40960, F, zp)])) == (0, 256 + 2 * 2 * (65536 + 40960) * 8)
+    # the same validation as the plan
+    d = _descs([(4096, L, lctp)])
+    d["prec"] = 1
+    assert _ws(lib, d) == (_lib.LCT_ERR_UNSUPPORTED, 0)
+    d = _descs([(4096, L, lctp), (4096, L, lctp)])
+    d["prec"][1] = 1
+    assert _ws(lib, d) == (_lib.LCT_ERR_ARG, 0)
+    d = _descs([(4096, L, lctp)])
+    d["pad"] = 1
+    assert _ws(lib, d) == (_lib.LCT_ERR_ARG, 0)
+    assert _ws(lib, _descs([(4097, L, lctp)]))[0] == _lib.LCT_ERR_UNSUPPORTED_N
+    assert _ws(lib, _descs([(4096, L, [1.0, 2.0, 0.5, 2.1])]))[0] == _lib.LCT_ERR_NOT_UNIMODULAR
+    assert _ws(lib, _descs([(4096, F, [0.9, 0.9, 0.0, 0.0])]))[0] == _lib.LCT_ERR_DOMAIN
+    assert _ws(lib, _descs([(4096, 2, lctp)]))[0] == _lib.LCT_ERR_ARG
+    assert lib.lct_workspace_size(None, 1, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_workspace_size(None, 3, ctypes.byref(ctypes.c_size_t())) == _lib.LCT_ERR_ARG
+
+
+def test_check_entry_points_reject_bad_arguments(lib):
+    """The device-side parameter checks validate their own arguments on the host
+    (nothing is enqueued on error)."""
+    assert lib.lct_check_params(7, 8, 1, 8, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_params(0, 8, 1, None, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_params(0, None, 1, 8, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_params(0, 12, 1, 8, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_params(1, 8, -1, 8, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_desc(None, 1, 8, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_desc(8, 1, 12, None) == _lib.LCT_ERR_ARG
+    assert lib.lct_check_desc(8, -2, 8, None) == _lib.LCT_ERR_ARG
+
+
+def test_fractional_order_slack_is_accepted(lib):
+    """|z| <= 1 + 1e-12 passes the host check (it is projected onto the unit circle);
+    beyond it, LCT_ERR_DOMAIN."""
+    rc, h = plan(lib)
+    assert lib.frft_exec(h, 1.0 + 2e-12, 0.0, 8, 16, 1, None) == _lib.LCT_ERR_DOMAIN
+    assert lib.frft_exec(h, 0.6, 0.8 + 5e-13, 0, 0, 0, None) == _lib.LCT_OK  # empty batch, order accepted
+    lib.lct_plan_destroy(h)
+
+
+def _same_grid_rc(lib, a, b, d, N=64):
+    a, b, d = complex(a), complex(b), complex(d)
+    return lib.lct_same_grid_exec(N, 0, a.real, a.imag, b.real, b.imag, d.real, d.imag, None, None, 0, None, 0,
+                                  None)
+
+
+def test_same_grid_domain_inequalities(lib):
+    """The complex-matrix same-grid LCT (the integral of §1 for complex a, b, d) is
+    accepted exactly where the Toeplitz form (Im b <= 0, Im[(a-1) b*] >= 0,
+    Im[(d-1) b*] >= 0) or the Hankel form (Im b >= 0, Im[(a+1) b*] >= 0,
+    Im[(d+1) b*] >= 0) has bounded factors; both sides of each inequality."""
+    ok, dom = _lib.LCT_OK, _lib.LCT_ERR_DOMAIN
+    # real matrices: every inequality holds with equality
+    assert _same_grid_rc(lib, 0.7, np.pi / 4, 1.3) == ok
+    assert _same_grid_rc(lib, -1.5, -0.8, 0.4) == ok
+    # Toeplitz form, b = 0.6 - 0.2i (Im b < 0): Im[(a-1) b*] = 0.6 Im a + 0.2 Re(a-1)
+    b = 0.6 - 0.2j
+    t = lambda a: float(np.imag((a - 1) * np.conj(b)))
+    a_in, a_out = 0.9 + 0.1j, 0.9 - 0.1j
+    assert t(a_in) > 0 > t(a_out)
+    assert _same_grid_rc(lib, a_in, b, 1.1 + 0.05j) == ok
+    assert _same_grid_rc(lib, a_out, b, 1.1 + 0.05j) == dom
+    assert _same_grid_rc(lib, a_in, b, 1.1 - 0.2j) == dom        # Im[(d-1) b*] < 0
+    # on the boundary Im[(a-1) b*] = 0 (a - 1 a real multiple of b) and 1e-6 beyond it
+    a_edge = 1 + 0.5 * b
+    assert _same_grid_rc(lib, a_edge, b, 1.1 + 0.05j) == ok
+    assert _same_grid_rc(lib, a_edge - 1e-6j, b, 1.1 + 0.05j) == dom
+    # Hankel form, b = 0.7 + 0.1i (Im b > 0): Im[(a+1) b*] >= 0, Im[(d+1) b*] >= 0
+    b = 0.7 + 0.1j
+    h = lambda a: float(np.imag((a + 1) * np.conj(b)))
+    assert h(1.2 + 0.5j) > 0 and h(0.3 + 0.6j) > 0
+    assert _same_grid_rc(lib, 1.2 + 0.5j, b, 0.3 + 0.6j) == ok
+    assert h(1.2 - 0.5j) < 0
+    assert _same_grid_rc(lib, 1.2 - 0.5j, b, 0.3 + 0.6j) == dom
+    # Im b = 0 with complex a: Toeplitz needs Im[(a-1) b] >= 0, i.e. Im a >= 0 for b > 0
+    assert _same_grid_rc(lib, 0.5 + 0.3j, 1.0, 0.5) == ok
+    assert _same_grid_rc(lib, 0.5 - 0.3j, 1.0, 0.5) == dom
+    # the bilateral Laplace matrix (0, i, i, 0): neither form
+    assert _same_grid_rc(lib, 0.0, 1j, 0.0) == dom
