@@ -177,7 +177,64 @@ def cpu_baseline(xh: np.ndarray, M: np.ndarray, outs: dict, budget_s: float):
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"{done} of the {xh.shape[0]} signals (N={N}, full dense Riemann sums), {el:.1f} s",
+        "single_thread": oracle_single_thread(lambda: oracle.lct(xh[0].astype(np.complex128), *M[0]), N,
+                                              f"signal 0 (N={N}, full dense Riemann sum)"),
     }, errs
+
+
+def oracle_single_thread(fn, samples: int, what: str) -> dict:
+    """The same oracle call on one thread: complex samples/s and what was timed."""
+    import oracle
+
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        fn()
+        el = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": samples / el, "unit": "complex samples/s", "cores": 1, "sample": f"{what}, {el:.1f} s"}
+
+
+def lct_energy_rows(M, gp, N, nrow, seed):
+    """Rows where a chirped Gaussian's LCT has its energy (from the Gaussian
+    integral's modulus; it only picks rows) plus random rows."""
+    a, b, c, d = M
+    mu, sigma, kappa = gp
+    al = 1 / (2 * sigma ** 2) - 1j * kappa
+    be = -mu / (2 * sigma ** 2)
+    if b == 0.0:
+        return np.random.default_rng(seed).choice(N, min(N, nrow), replace=False)
+    yn = 4.0 * b * oracle_nodes(N) / np.pi
+    logmag = np.real((be + 1j * yn / (2 * b)) ** 2 / (al - 1j * a / (2 * b)))
+    top = np.argsort(-logmag)[: nrow // 2]
+    rnd = np.random.default_rng(seed).choice(N, nrow - nrow // 2, replace=False)
+    return np.unique(np.concatenate([top, rnd]))
+
+
+def frft_energy_rows(gp, z, N, nrow, seed):
+    """Rows where a chirped Gaussian's same-grid fractional transform has its
+    energy (Gaussian integral of eq. fasy's kernel) plus random rows."""
+    mu, sigma, kappa = gp
+    al = 1 / (2 * sigma ** 2) - 1j * kappa
+    be = -mu / (2 * sigma ** 2)
+    y = oracle_nodes(N)
+    if abs(1 - z * z) < 1e-12:
+        logmag = np.real(-(al * y * y + 2 * be * y))
+    else:
+        A = (1 + z * z) / (2 * (1 - z * z)) + al
+        B = y * z / (1 - z * z) - be
+        logmag = np.real(B * B / A - (1 + z * z) * y * y / (2 * (1 - z * z)))
+    top = np.argsort(-logmag)[: nrow // 2]
+    rnd = np.random.default_rng(seed).choice(N, nrow - nrow // 2, replace=False)
+    return np.unique(np.concatenate([top, rnd]))
+
+
+def oracle_nodes(N):
+    import oracle
+
+    return oracle.nodes(N)
 
 
 def bench_ragged(args):
@@ -207,7 +264,8 @@ def bench_ragged(args):
     ms, ms_kernel, wall = time_launches(lambda: lct.lct_exec_ragged(plan, x, out=y), args.steps, args.warmup)
     samples = int(N.sum())
     gbps = 16.0 * samples / (ms_kernel * 1e-3) / 1e9
-    return {
+    errors = None if args.no_cpu_baseline else ragged_errors(x, y, desc, kinds, N, params, gp, lct)
+    out = {
         "metric": "complex samples/s, ragged batch in one persistent launch",
         "value": samples / (ms * 1e-3), "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -220,6 +278,62 @@ def bench_ragged(args):
                      "algorithmic_bytes_per_launch": 16.0 * samples},
         "wall_s_timed": wall,
     }
+    if errors is not None:
+        out["rel_l2"], out["cpu_baseline"] = errors
+    return out
+
+
+def ragged_errors(x, y, desc, kinds, N, params, gp, lct):
+    """Relative L2 error of the ragged launch against the oracle on a seeded
+    sample: two signals per (kind, length band), short (in LDS), middle and long
+    (four-step inside one work-group); every output up to N = 4096, else 128
+    rows (energy rows plus random rows).  Also the oracle's rate on them."""
+    import oracle
+
+    xh = x.cpu().numpy()
+    yh = y.cpu().numpy()
+    gs = np.random.default_rng(1379)
+    pick = []
+    for kind in (lct.LCT_KIND_LCT, lct.LCT_KIND_FRFT):
+        for lo, hi in ((256, 2048), (2049, 16384), (16385, 65536)):
+            cand = np.flatnonzero((kinds == kind) & (N >= lo) & (N <= hi))
+            if cand.size:
+                pick.extend(int(i) for i in gs.choice(cand, min(2, cand.size), replace=False))
+    errs = {"lct": [], "frft": []}
+    worst = {"lct": None, "frft": None}
+    done = 0
+    t0 = time.perf_counter()
+    for i in pick:
+        n, o = int(N[i]), int(desc["offset"][i])
+        fin = xh[o:o + n].astype(np.complex128)
+        got = yh[o:o + n].astype(np.complex128)
+        name = "lct" if kinds[i] == lct.LCT_KIND_LCT else "frft"
+        if name == "lct":
+            rows = None if n <= 4096 else lct_energy_rows(params[i], gp[i], n, 128, i)
+            ref = oracle.lct(fin, *params[i], rows=rows)
+        else:
+            z = complex(params[i][0], params[i][1])
+            rows = None if n <= 4096 else frft_energy_rows(gp[i], z, n, 128, i)
+            ref = oracle.frft(fin, z, rows=rows)
+        g = got if rows is None else got[rows]
+        e = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        errs[name].append(e)
+        if worst[name] is None or e > worst[name][0]:
+            worst[name] = (e, n)
+        done += n * (n if rows is None else len(rows))
+    el = time.perf_counter() - t0
+    rel = {k: {"max": max(v), "median": float(np.median(v)), "signals": len(v), "worst_N": worst[k][1]}
+           for k, v in errs.items() if v}
+    rel["rows"] = "every output up to N = 4096, else 128 rows (64 where the output has its energy, 64 random)"
+    # the oracle's rate on the whole batch, from its measured multiply-add rate:
+    # a dense transform of length n costs n^2 of them
+    mac_rate = done / el
+    whole = float(np.sum(N.astype(np.float64) ** 2)) / mac_rate
+    cb = {"value": float(N.sum()) / whole, "unit": "complex samples/s", "cores": oracle.num_threads(),
+          "kind": "oracle",
+          "sample": f"{len(pick)} signals of the batch (2 per kind and length band; {done:.3g} multiply-adds "
+                    f"in {el:.1f} s), scaled to the whole batch's sum of N^2 ({whole:.0f} s)"}
+    return rel, cb
 
 
 def bench_large(args):
@@ -271,18 +385,8 @@ def bench_large(args):
     if not args.no_cpu_baseline:
         import oracle
 
-        # rows where the chirped Gaussian's transform has its energy (from the
-        # Gaussian integral's modulus; it only picks rows) plus random rows
         def energy_rows(s, nrow=64):
-            a, b, c, d = M[s]
-            mu, sigma, kappa = gp[s]
-            al = 1 / (2 * sigma ** 2) - 1j * kappa
-            be = -mu / (2 * sigma ** 2)
-            _, yn = lct.lct_nodes(N, b, d)
-            logmag = np.real((be + 1j * yn / (2 * b)) ** 2 / (al - 1j * a / (2 * b)))
-            top = np.argsort(-logmag)[: nrow // 2]
-            rnd = np.random.default_rng(4 + s).choice(N, nrow - nrow // 2, replace=False)
-            return np.unique(np.concatenate([top, rnd]))
+            return lct_energy_rows(M[s], gp[s], N, nrow, 4 + s)
         errs32, errs64, errsp = [], [], []
         t0 = time.perf_counter()
         for s in range(2):
@@ -486,7 +590,7 @@ def bench_fit(args):
         loss.backward()
 
     ms, ms_kernel, wall = time_launches(step, args.steps, args.warmup)
-    return {
+    out = {
         "metric": "steps/s, differentiable LCT fit (forward + backward)",
         "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -495,6 +599,41 @@ def bench_fit(args):
                    "signals": B, "N": N},
         "roofline": None, "wall_s_timed": wall,
     }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        # one step's three products on sampled signals, against the oracle: the
+        # forward transform, the input gradient (adjoint of the output gradient)
+        # and the parameter gradient, with the output gradient of this loss,
+        # g = 4 (|y|^2 - I) y, formed from the GPU forward (an input to both sides)
+        with torch.no_grad():
+            y = lct.lct(fp, Mp)
+            gy = (4 * (y.abs() ** 2 - target) * y).contiguous()
+            gf = lct.lct_exec_many_adjoint(gy, Mp.detach())
+            gM = lct.lct_param_grad_many(fp.detach(), gy, Mp.detach())
+        fh, yh, gyh = fp.detach().cpu().numpy(), y.cpu().numpy(), gy.cpu().numpy()
+        gfh, gMh, Mh = gf.cpu().numpy(), gM.cpu().numpy(), Mp.detach().cpu().numpy()
+        ef, eg, ep = [], [], []
+        t0 = time.perf_counter()
+        nsig = 0
+        while nsig < B and (nsig < 2 or time.perf_counter() - t0 < args.cpu_budget):
+            s = nsig
+            fin, gin = fh[s].astype(np.complex128), gyh[s].astype(np.complex128)
+            ref = oracle.lct(fin, *Mh[s])
+            ef.append(float(np.linalg.norm(yh[s] - ref) / np.linalg.norm(ref)))
+            refg = oracle.lct_adjoint(gin, *Mh[s])
+            eg.append(float(np.linalg.norm(gfh[s] - refg) / np.linalg.norm(refg)))
+            refp = oracle.lct_param_grad(fin, gin, *Mh[s])
+            ep.append(float(np.abs(gMh[s] - refp).max() / np.abs(refp).max()))
+            nsig += 1
+        el = time.perf_counter() - t0
+        out["rel_l2"] = {"forward_max": max(ef), "input_grad_max": max(eg), "param_grad_max_rel": max(ep),
+                         "signals": nsig}
+        out["cpu_baseline"] = {"value": nsig / el / B, "unit": "steps/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{nsig} of the {B} signals (forward, adjoint and parameter gradient, "
+                                         f"dense N={N} sums), {el:.1f} s, scaled to the {B}-signal step"}
+    return out
 
 
 def main():

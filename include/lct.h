@@ -356,7 +356,7 @@ void lct_tune_clear(void);
  * significant bits per product).  The weights sqrt(2 pi) z^n are formed on
  * the device in double-double.
  *
- * xft_plan_create computes the zeros (QL eigenvalues of the symmetric
+ * xft_plan_create computes the zeros (QR eigenvalues of the symmetric
  * tridiagonal H of §2, polished by Newton steps) and U (recurrence of eq.
  * receqg, normalised by the Christoffel-Darboux sum) on the host and keeps U
  * and U^T in plan-owned DEVICE memory (2 N^2 values of the plan's precision,

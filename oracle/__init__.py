@@ -89,6 +89,8 @@ def _load():
     lib.oracle_hermite_vectors.argtypes = [i64, _dp, _dp]
     lib.oracle_Fz_exact.argtypes = [i64, _dp, d, d, _dp]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -104,6 +106,11 @@ def _ptr(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (for timing the oracle on one core)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def nodes(N: int) -> np.ndarray:

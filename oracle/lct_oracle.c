@@ -553,3 +553,17 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads of later calls (for timing on one core).
+ * Each output row is summed by one thread, so the rows do not depend on it;
+ * only the parameter gradient's reduction over rows is ordered by it. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
