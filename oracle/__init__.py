@@ -24,6 +24,14 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             fractional transform (a = d), O1 at b = pi/4 for
                             real matrices, the complex Gaussian closed form
                             and mpmath brute force.
+``trig_interp(f, p)``       trigonometric interpolation of the samples onto the
+                            grid of step h / p; pinned by exact reproduction of
+                            trigonometric polynomials and by the explicit
+                            periodic-interpolation sum.
+``lct_oversampled(f, a, b, c, d, p)``  aliasing-aware LCT: O1 on that finer
+                            grid at the Algorithm's output nodes; pinned by
+                            p = 1 (O1), the chirped-Gaussian closed form where
+                            O1 aliases, and the explicit interpolation sum.
 ``lct_adjoint``             conjugate transpose of the same matrix; pinned by
                             the inner-product identity and unitarity.
 ``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d)
@@ -153,6 +161,63 @@ def lct(f, a: float, b: float, c: float, d: float, rows=None, scale: float = 1.0
     if rc != 0:
         raise ValueError(f"oracle_lct_rows failed ({rc})")
     return out
+
+
+def trig_interp(f, p: int) -> np.ndarray:
+    """Trigonometric interpolation of the samples f_k = f(x_k) (eq. asymcer's
+    grid, step h, period N h) onto the grid of step h / p over the same span,
+    xi_m = (h / p)(m - (p N - 1) / 2), m < p N:
+        f(x) = sum_n c_n exp(2 pi i n (x - x_0) / (N h)),  c_n = (1/N) sum_k f_k e^{-2 pi i n k / N},
+    n over -N/2 .. N/2 (for even N the coefficient of n = +-N/2 split in two
+    halves).  At xi_m, (xi_m - x_0) / (N h) = (m - (p - 1)/2) / (p N), so the fine
+    samples are a length-pN inverse DFT of the twisted coefficients.  numpy's
+    FFT serves as the DFT."""
+    f = _cplx_in(f)
+    N = f.shape[0]
+    p = int(p)
+    if p < 1:
+        raise ValueError("p >= 1")
+    if p == 1:
+        return f.copy()
+    M = p * N
+    c = np.fft.fft(f) / N
+    n = np.arange(N)
+    n = np.where(n < (N + 1) // 2, n, n - N)  # -floor(N/2) .. ceil(N/2) - 1
+    twist = lambda k: np.exp(-1j * np.pi * k * (p - 1) / M)
+    dpad = np.zeros(M, dtype=np.complex128)
+    if N % 2 == 0:
+        nyq = N // 2
+        half = c[nyq] / 2  # c at n = -N/2 (index N/2 of the DFT)
+        keep = n != -nyq
+        dpad[n[keep] % M] = c[keep] * twist(n[keep])
+        dpad[(-nyq) % M] += half * twist(-nyq)
+        dpad[nyq % M] += half * twist(nyq)
+    else:
+        dpad[n % M] = c * twist(n)
+    return np.fft.ifft(dpad) * M
+
+
+def lct_oversampled(f, a: float, b: float, c: float, d: float, p: int, rows=None) -> np.ndarray:
+    """Aliasing-aware discrete LCT: the samples f_k on x_k are interpolated
+    trigonometrically onto the grid of step h / p (trig_interp), and the
+    Riemann sum of the integral of §1 is taken there (weight h / p), at the
+    Algorithm's output nodes y_j = 4 b x_j / pi.  That fine grid is the scaled
+    grid s x'_m of p N points with s = 1 / sqrt(p) (x'_m eq. asymcer's nodes
+    for p N), whose output nodes 4 b x'_m / (pi s) hold the y_j as the middle
+    block m = j + (p - 1) N / 2; so this is O1 on the scaled grid (lct with
+    scale = s) at those rows.  For b = 0 (a diagonal, no aliasing) it is O1
+    itself; p = 1 is O1."""
+    f = _cplx_in(f)
+    N = f.shape[0]
+    if b == 0.0 or int(p) == 1:
+        return lct(f, a, b, c, d, rows=rows)
+    p = int(p)
+    if ((p - 1) * N) % 2:
+        raise ValueError("(p - 1) N must be even (the y_j then sit on the fine output grid)")
+    g = trig_interp(f, p)
+    off = (p - 1) * N // 2
+    r = np.arange(N) if rows is None else np.asarray(rows, dtype=np.int64)
+    return lct(g, a, b, c, d, rows=r + off, scale=1.0 / np.sqrt(p))
 
 
 def lct_same_grid(f, a: complex, b: complex, d: complex, rows=None) -> np.ndarray:
