@@ -194,6 +194,24 @@ int frft_exec_many_ws(int64_t N, lct_precision prec, const double *Z2, const voi
                       int64_t batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * frft_exec_ws without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the workspace is a library-owned static device
+ * array of LCT_NOALLOC_SCRATCH_BYTES per device (obtained once per device,
+ * held until the process ends).  The call allocates nothing.  Same transform,
+ * arguments and errors as frft_exec; a batch whose workspace,
+ * frft_workspace_size(N, prec, batch), exceeds LCT_NOALLOC_SCRATCH_BYTES gives
+ * LCT_ERR_WORKSPACE (FP32: e.g. 32 signals at N = 65536, 128 at 16384; single-pass
+ * lengths need only 2N complex values for any batch).  Every call on one
+ * device shares that device's array: calls that overlap in time on one device
+ * (different streams, or different host threads) race and must be serialised
+ * by the caller.  Nothing in the array needs to start at zero.
+ */
+#define LCT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int frft_exec_noalloc(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,
+                      hipStream_t stream);
+
+/*
  * LCT of §1 for a complex matrix (a, b, d complex, b != 0; c follows from
  * ad - bc = 1 and does not enter), e.g. damped LCTs, with the output on the
  * input grid (y_j = x_j, eq. asymcer), as the Riemann sum of the integral:

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/lct.h"
@@ -354,6 +355,37 @@ int frft_large_launch(const FsTiling &f, int64_t N, bool fp64, const double *Z2,
 
 } // namespace lctk
 
+namespace {
+
+// Workspace of frft_exec_noalloc: one array per device, held until the process
+// ends.  In host code `scratch` only names the symbol; its device address comes
+// from hipGetSymbolAddress, once per device with that device current.
+__device__ __align__(256) unsigned char scratch[LCT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 256;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];
+
+int scratch_of_current_device(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return LCT_ERR_HIP;
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return LCT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return LCT_ERR_HIP;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return LCT_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 int64_t lct_max_single_pass(lct_precision prec) { return single_pass_limit(prec == LCT_FP64); }
@@ -519,6 +551,31 @@ int frft_exec_ws(lct_plan p, double z_re, double z_im, const void *in, void *out
         return rc;
     FrConst k = fr_const(p->N, z_re, z_im);
     return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, ws_bytes, stream);
+}
+
+int frft_exec_noalloc(lct_plan p, double z_re, double z_im, const void *in, void *out, int64_t batch,
+                      hipStream_t stream)
+{
+    if (!p)
+        return LCT_ERR_ARG;
+    if (p->prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
+    if (p->s != 1.0)
+        return LCT_ERR_UNSUPPORTED;
+    if (int rc = validate_z(z_re, z_im))
+        return rc;
+    if (batch < 0)
+        return LCT_ERR_ARG;
+    const size_t need = frft_ws_bytes(p->N, p->prec == LCT_FP64, batch);
+    if (need > LCT_NOALLOC_SCRATCH_BYTES)
+        return LCT_ERR_WORKSPACE;
+    if (batch == 0)
+        return LCT_OK;
+    void *ws = nullptr;
+    if (int rc = scratch_of_current_device(&ws))
+        return rc;
+    FrConst k = fr_const(p->N, z_re, z_im);
+    return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, need, stream);
 }
 
 int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im,
