@@ -597,6 +597,37 @@ __device__ __forceinline__ void fft_lds_fixed(C<R> *v, C<R> *lds, int t)
     fft_lds_fixed_from<E, N, 0, 1>(v, lds, t);
 }
 
+// Same transform with the exchanges alternating between two LDS buffers.
+// Exchange k writes buffer k mod 2, waits at one barrier and reads it back:
+// the buffer it overwrites was last read in exchange k - 2, and every thread
+// finished that read before writing exchange k - 1, i.e. before the barrier
+// of exchange k - 1 that this thread has passed.  One barrier per stage
+// instead of two.  `par` carries the alternation across calls (start it at 0
+// and pass the same variable to every FFT of the kernel).
+template <int E, int N, int S, int NS, typename R>
+__device__ __forceinline__ void fft_lds_fixed2_from(C<R> *v, C<R> *lds0, C<R> *lds1, int t, int &par)
+{
+    constexpr int NST = fixed_nstages(N, E);
+    if constexpr (S < NST) {
+        constexpr int RAD = fixed_radix(N, E, S);
+        constexpr int T = N / E;
+        stage_compute<E, RAD>(v, t, T, NS);
+        if constexpr (S + 1 < NST) {
+            C<R> *buf = par ? lds1 : lds0;
+            par ^= 1;
+            stage_write<E, RAD>(buf, v, t, T, NS);
+            __syncthreads();
+            stage_read<E>(buf, v, t, T);
+        }
+        fft_lds_fixed2_from<E, N, S + 1, NS * RAD>(v, lds0, lds1, t, par);
+    }
+}
+template <int E, int N, typename R>
+__device__ __forceinline__ void fft_lds_fixed2(C<R> *v, C<R> *lds0, C<R> *lds1, int t, int &par)
+{
+    fft_lds_fixed2_from<E, N, 0, 1>(v, lds0, lds1, t, par);
+}
+
 // Same transform with each exchange made in two halves, the real parts and
 // then the imaginary parts, through a buffer of lds_elems(N) R (half the LDS
 // of the whole-value exchange, for two more barriers per stage).

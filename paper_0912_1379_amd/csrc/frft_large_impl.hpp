@@ -21,7 +21,7 @@ enum FrKind { FR_DATA = 0, FR_KERN = 1 };
 template <typename R>
 __device__ __forceinline__ FrConst fr_const_of(const FrLArgs &a, int64_t s)
 {
-    return a.Z2 != nullptr ? fr_const(a.N, a.Z2[2 * s], a.Z2[2 * s + 1]) : a.k;
+    return a.Z2 != nullptr ? fr_const(a.N, a.Z2[2 * s], a.Z2[2 * s + 1], sizeof(R) == 8) : a.k;
 }
 
 // Pass 1 over columns n2 of the length-L sequence (element i = n1 L2 + n2).
@@ -52,21 +52,29 @@ __global__ __launch_bounds__(LB) void k_frl1(
     V *R0 = ws + (size_t)s * 2 * L;
     V *R1 = R0 + L;
 
+    // element i = (t + T1 e) L2 + n2
     C<R> v[E];
+    const int i0 = t * L2 + n2, Di = T1 * L2;
+    if (kind == FR_DATA) {
+        // e^{-P x_i^2} f_i, n_i = 2i - N + 1, zero beyond N
+        GaussSeq<R> dch(k.dmag, k.dph_hi, k.dph_lo, 2 * i0 - N + 1, 2 * Di);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = (t + T1 * e) * L2 + n2;
-        C<R> x = {(R)0, (R)0};
-        if (kind == FR_DATA) {
-            if (i < N && !k.special) {
-                x = ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i));
-                x = cmul(x, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(i, N)));
-            }
-        } else {
-            const int m = i <= N ? i : L - i;
-            x = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, (double)m * (double)m);
+        for (int e = 0; e < E; ++e) {
+            const int i = i0 + Di * e;
+            const C<R> w = dch.next();
+            C<R> x = {(R)0, (R)0};
+            if (i < N && !k.special)
+                x = cmul(ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i)), w);
+            v[e] = x;
         }
-        v[e] = x;
+    } else {
+        // kernel at m = i for i <= N, m = L - i = (L - i0) - Di e beyond
+        GaussSeq<R> lo(k.kmag, k.kph_hi, k.kph_lo, i0, Di), hi(k.kmag, k.kph_hi, k.kph_lo, L - i0, -Di);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<R> a = lo.next(), b = hi.next();
+            v[e] = i0 + Di * e <= N ? a : b;
+        }
     }
 
     C<R> *lds = smem + (size_t)sl * lds_elems(L1);
@@ -187,13 +195,16 @@ __global__ __launch_bounds__(LB) void k_frl3(const typename Vec<R>::T *__restric
     const int sl2 = tid % Cc;
     const int t2 = tid / Cc;
     const C<R> *l2 = smem + (size_t)sl2 * lds_elems(L1);
+    // output j = (n20 + sl2 + L2 t2) + L2 T1 e, the first N kept
+    const int j0 = n20 + sl2 + L2 * t2;
+    GaussSeq<R> och(k.omag, k.oph_hi, k.oph_lo, 2 * j0 - N + 1, 2 * L2 * T1);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n1 = t2 + T1 * e;
-        const int j = n20 + sl2 + L2 * n1;
+        const int j = j0 + L2 * T1 * e;
+        const C<R> w = och.next();
         if (j < N) {
-            C<R> y = cconj(l2[lds_pad(n1)]);
-            y = cmul(y, gauss_chirp<R>(k.omag, k.oph_hi, k.oph_lo, nsq(j, N)));
+            C<R> y = cmul(cconj(l2[lds_pad(n1)]), w);
             y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
             stc<R>(out + (size_t)s * N + j, y);
         }

@@ -371,16 +371,74 @@ __device__ __forceinline__ C<R> gauss_chirp(double mag_per, double ph_hi, double
     return cscale(c, s);
 }
 
+// The Gaussian-chirp values exp(mag m^2) cis(ph m^2) of one thread at
+// m_e = m0 + D e, e = 0, 1, 2, ... in order (next() once per e).  The turns
+// ph m_e^2 are the quadratic A + e B + e^2 C whose coefficients are formed
+// once per thread from the exact integers m0^2, 2 m0 D and D^2 and reduced
+// modulo 1 in double-double (as quad_turns does for m^2 itself), so a value
+// costs two FP64 fused multiply-adds and one reduction instead of a
+// double-double product.  The log-modulus mag m_e^2 is formed from the exact
+// m_e^2 (a quadratic in e would cancel large terms where m0 is large and m_e
+// small).  FP32 evaluates the phase with the hardware sine/cosine; FP64 walks
+// it by products (as ChirpSeq<double>, about 2 e^2 rounding units after e
+// steps).
+struct GaussPoly {
+    double mag;
+    int m0, D;
+    ThreadChirp ph; // turns
+};
+__device__ __forceinline__ GaussPoly gauss_poly(double mag_per, double ph_hi, double ph_lo, int m0, int D)
+{
+    const double a = (double)m0 * (double)m0, b = 2.0 * (double)m0 * (double)D, c = (double)D * (double)D;
+    const Quad q{ph_hi, ph_lo};
+    return {mag_per, m0, D, {frac_turns(quad_turns(q, a)), frac_turns(quad_turns(q, b)), frac_turns(quad_turns(q, c))}};
+}
+__device__ __forceinline__ double gauss_logmod(const GaussPoly &g, int e)
+{
+    const double m = (double)(g.m0 + g.D * e);
+    return g.mag * (m * m);
+}
+// FP32: the value at any e (no state beyond the coefficients).
+__device__ __forceinline__ C<float> gauss_at(const GaussPoly &g, int e)
+{
+    return cscale(chirp_at<float>(g.ph, e), expf((float)fmax(gauss_logmod(g, e), -200.0)));
+}
+template <typename R> struct GaussSeq;
+template <> struct GaussSeq<float> {
+    GaussPoly g;
+    int e;
+    __device__ GaussSeq(double mag_per, double ph_hi, double ph_lo, int m0, int D)
+        : g(gauss_poly(mag_per, ph_hi, ph_lo, m0, D)), e(0)
+    {
+    }
+    __device__ __forceinline__ C<float> next() { return gauss_at(g, e++); }
+};
+template <> struct GaussSeq<double> {
+    GaussPoly g;
+    ChirpSeq<double> c;
+    int e;
+    __device__ GaussSeq(double mag_per, double ph_hi, double ph_lo, int m0, int D)
+        : g(gauss_poly(mag_per, ph_hi, ph_lo, m0, D)), c(g.ph), e(0)
+    {
+    }
+    __device__ __forceinline__ C<double> next() { return cscale(c.next(), exp(fmax(gauss_logmod(g, e++), -1000.0))); }
+};
+
 // Launch bound of a fixed-length instantiation (E = 16): the work-group of the
 // default geometry, max(256, length / 16) threads, so that the register
 // budget is not cut to what 1024 threads would allow.
 constexpr int tight_bound(int n) { return n / 16 > 256 ? n / 16 : 256; }
 
-// The in-LDS FFT with a compile-time schedule when NF > 0, else the runtime one.
-template <typename R, int E, int NF>
-__device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const Sched &sc)
+// The in-LDS FFT with a compile-time schedule when NF > 0, else the runtime
+// one; DB: the double-buffered exchange (lds1 the second buffer, par the
+// alternation state shared by the kernel's FFTs).
+template <typename R, int E, int NF, bool DB = false>
+__device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const Sched &sc, C<R> *lds1 = nullptr,
+                                        int *par = nullptr)
 {
-    if constexpr (NF > 0)
+    if constexpr (DB)
+        fft_lds_fixed2<E, NF>(v, lds, lds1, t, *par);
+    else if constexpr (NF > 0)
         fft_lds_fixed<E, NF>(v, lds, t);
     else
         fft_lds<E>(v, lds, t, T, sc);
@@ -392,7 +450,11 @@ __device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const 
 // holding it in registers through the data's FFT; with those registers free
 // it is asked for four waves per SIMD (two 512-thread work-groups per CU at
 // L = 8192, against one for the kernel that transforms its own spectrum).
-template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool SREAD = false>
+// DB (fixed lengths): the FFT exchanges alternate between two LDS buffers
+// (twice the LDS, one barrier per stage); used where the registers already
+// hold the work-group to one per CU.
+template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool SREAD = false,
+          bool DB = false>
 __global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FrArgs args)
 {
@@ -408,8 +470,10 @@ __global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
     const int64_t sig = (int64_t)blockIdx.x * args.S + sl;
     const bool live = sig < args.batch;
     C<R> *lds = smem + (size_t)sl * lds_elems(L);
+    C<R> *lds1 = DB ? smem + (size_t)(args.S + sl) * lds_elems(L) : nullptr;
+    int par = 0;
     const int64_t ss = live ? sig : 0;
-    FrConst k = args.Z2 ? fr_const(N, args.Z2[2 * ss], args.Z2[2 * ss + 1]) : args.k;
+    FrConst k = args.Z2 ? fr_const(N, args.Z2[2 * ss], args.Z2[2 * ss + 1], sizeof(R) == 8) : args.k;
     const V *src = in + (size_t)ss * N;
     V *dst = out + (size_t)ss * N;
 
@@ -437,14 +501,13 @@ __global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
         for (int e = 0; e < E; ++e)
             K[e] = ldc<R>(sp + t + T * e);
     } else {
+        // m = p = t + T e for e < E/2, m = L - p = (N - t) - T (e - E/2) after
+        // (the position p = N is never used by an output j < N)
+        GaussSeq<R> lo(k.kmag, k.kph_hi, k.kph_lo, t, T), hi(k.kmag, k.kph_hi, k.kph_lo, N - t, -T);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = t + T * e;
-            const int m = p <= N ? p : L - p;
-            const double m2 = (double)m * (double)m;
-            K[e] = gauss_chirp<R>(k.kmag, k.kph_hi, k.kph_lo, m2);
-        }
-        fft_any<R, E, LFIX>(K, lds, t, T, sc);
+        for (int e = 0; e < E; ++e)
+            K[e] = e < E / 2 ? lo.next() : hi.next();
+        fft_any<R, E, LFIX, DB>(K, lds, t, T, sc, lds1, &par);
         if (args.spec_mode == SPEC_WRITE) {
             // launched as one work-group; slot 0 holds the spectrum
             if (sl == 0) {
@@ -458,18 +521,23 @@ __global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
     }
 
     // 2) data e^{-P x_k^2} f_k (reversed for Hankel), zero-padded to L
+    // (n_p = 2p - N + 1 = (2t - N + 1) + 2T e)
     C<R> v[E];
+    {
+        GaussSeq<R> dch(k.dmag, k.dph_hi, k.dph_lo, 2 * t - N + 1, 2 * T);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int p = t + T * e;
-        C<R> x = {(R)0, (R)0};
-        if (e < E / 2 && live && !k.special) { // p < N  <=>  e < E/2
-            x = ldc<R>(src + (k.hankel ? N - 1 - p : p));
-            x = cmul(x, gauss_chirp<R>(k.dmag, k.dph_hi, k.dph_lo, nsq(p, N)));
+        for (int e = 0; e < E; ++e) {
+            const int p = t + T * e;
+            C<R> x = {(R)0, (R)0};
+            if (e < E / 2) { // p < N  <=>  e < E/2
+                const C<R> w = dch.next();
+                if (live && !k.special)
+                    x = cmul(ldc<R>(src + (k.hankel ? N - 1 - p : p)), w);
+            }
+            v[e] = x;
         }
-        v[e] = x;
     }
-    fft_any<R, E, LFIX>(v, lds, t, T, sc);
+    fft_any<R, E, LFIX, DB>(v, lds, t, T, sc, lds1, &par);
 
     // 3) inverse DFT of the product: conj(FFT(conj(V K)))
     if constexpr (SREAD) {
@@ -482,14 +550,15 @@ __global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
         for (int e = 0; e < E; ++e)
             v[e] = cconj(cmul(v[e], K[e]));
     }
-    fft_any<R, E, LFIX>(v, lds, t, T, sc);
+    fft_any<R, E, LFIX, DB>(v, lds, t, T, sc, lds1, &par);
 
     if (live && !k.special) {
+        GaussSeq<R> och(k.omag, k.oph_hi, k.oph_lo, 2 * t - N + 1, 2 * T);
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int j = t + T * e;
             C<R> y = cconj(v[e]);
-            y = cmul(y, gauss_chirp<R>(k.omag, k.oph_hi, k.oph_lo, nsq(j, N)));
+            y = cmul(y, och.next());
             y = cmul(y, C<R>{(R)k.cre, (R)k.cim});
             stc<R>(dst + j, y);
         }
@@ -528,9 +597,15 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
                                 hipStream_t s)
 {
     auto kern = k_frft<R, E, LFIX, LB>;
-    if constexpr (LFIX > 0 && sizeof(R) == 4)
-        if (a.spec_mode == SPEC_READ)
+    if constexpr (LFIX > 0 && sizeof(R) == 4) {
+        if (a.spec_mode == SPEC_READ) {
             kern = k_frft<R, E, LFIX, LB, true>;
+        } else if (LFIX == 8192 && a.S == 1) {
+            // one work-group per CU by its registers: a second LDS buffer fits
+            kern = k_frft<R, E, LFIX, LB, false, true>;
+            lds *= 2;
+        }
+    }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,

@@ -312,7 +312,11 @@ __host__ __device__ inline void csqrt_principal(double re, double im, double &sr
     }
 }
 
-__host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
+// dd: P and beta in double-double (the host, and the FP64 kernels for
+// per-signal orders); the FP32 kernels take them in double (their phase rates
+// then carry a relative error of a few 1e-16, far below FP32 rounding, at a
+// fraction of the cost: every thread forms its signal's constants).
+__host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi, bool dd = true)
 {
     FrConst k{};
     // orders accepted just outside the unit circle (|z| <= 1 + 1e-12) are
@@ -331,13 +335,23 @@ __host__ __device__ inline FrConst fr_const(int64_t N, double zr, double zi)
     k.hankel = zr < 0.0 ? 1 : 0;
     double s = k.hankel ? -1.0 : 1.0; // z -> s z maps the Hankel case onto the Toeplitz formulas
     double wr = s * zr, wi = s * zi;
-    // P = (1 - w) / (2 (1 + w)), beta = w / (1 - w^2)  (w^2 = z^2), in
-    // double-double: their imaginary parts are phase rates per n^2 and m^2
-    const CDD P = cdd_div(CDD{dd_two_sum(1.0, -wr), DD{-wi, 0.0}},
-                          CDD{dd_mul_d(dd_two_sum(1.0, wr), 2.0), DD{2.0 * wi, 0.0}});
-    const CDD z2{dd_sub(dd_two_prod(zr, zr), dd_two_prod(zi, zi)), dd_mul_d(dd_two_prod(zr, zi), 2.0)};
-    const CDD om{dd_sub(DD{1.0, 0.0}, z2.re), dd_neg(z2.im)};
-    const CDD B = cdd_div(cdd_of(wr, wi), om);
+    // P = (1 - w) / (2 (1 + w)), beta = w / (1 - w^2)  (w^2 = z^2); their
+    // imaginary parts are phase rates per n^2 and m^2
+    CDD P, B, om;
+    if (dd) {
+        P = cdd_div(CDD{dd_two_sum(1.0, -wr), DD{-wi, 0.0}}, CDD{dd_mul_d(dd_two_sum(1.0, wr), 2.0), DD{2.0 * wi, 0.0}});
+        const CDD z2{dd_sub(dd_two_prod(zr, zr), dd_two_prod(zi, zi)), dd_mul_d(dd_two_prod(zr, zi), 2.0)};
+        om = CDD{dd_sub(DD{1.0, 0.0}, z2.re), dd_neg(z2.im)};
+        B = cdd_div(cdd_of(wr, wi), om);
+    } else {
+        double Pr, Pi, Br, Bi;
+        cdiv(1.0 - wr, -wi, 2.0 * (1.0 + wr), 2.0 * wi, Pr, Pi);
+        const double omr = 1.0 - (zr * zr - zi * zi), omi = -2.0 * zr * zi;
+        cdiv(wr, wi, omr, omi, Br, Bi);
+        P = cdd_of(Pr, Pi);
+        B = cdd_of(Br, Bi);
+        om = cdd_of(omr, omi);
+    }
     const double n = (double)N;
     const DD pi{PI_HI, PI_LO};
     // exp(-P x^2), x^2 = pi^2 n^2 / (8N)

@@ -56,6 +56,27 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
     lo = (__bf16)(x - (float)hi);
 }
 
+// The same split for the four complex operands of a lane, the real and
+// imaginary parts of each rounded as one pair (one packed conversion for the
+// two hi parts and one for the two lo parts).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void split4_bf16(const C<float> *u, bf16x8 &bh, bf16x8 &bl)
+{
+    u32x4v h4, l4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const f32x2 x = {u[i].x, u[i].y};
+        const bf16x2 h = __builtin_convertvector(x, bf16x2);
+        const bf16x2 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), bf16x2);
+        h4[i] = __builtin_bit_cast(unsigned int, h);
+        l4[i] = __builtin_bit_cast(unsigned int, l);
+    }
+    bh = __builtin_bit_cast(bf16x8, h4);
+    bl = __builtin_bit_cast(bf16x8, l4);
+}
+
 __device__ __forceinline__ Dft16Frag dft16_frag(int lane)
 {
     const int m = lane & 15, g = lane >> 4;
@@ -112,16 +133,7 @@ __device__ __forceinline__ void mfma_stage16(C<float> *smem, int P, int N, int N
                 u[i] = cmul(u[i], cis_turns(-(float)(j * (4 * g + i)) * inv));
         }
         bf16x8 bh, bl;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            __bf16 h, l;
-            split_bf16(u[i].x, h, l);
-            bh[2 * i] = h;
-            bl[2 * i] = l;
-            split_bf16(u[i].y, h, l);
-            bh[2 * i + 1] = h;
-            bl[2 * i + 1] = l;
-        }
+        split4_bf16(u, bh, bl);
         f32x4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
         // small terms first
         dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.re_hi, bl, dr, 0, 0, 0);

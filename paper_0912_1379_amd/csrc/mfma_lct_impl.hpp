@@ -21,16 +21,7 @@ namespace lctk {
 __device__ __forceinline__ void mfma_dft16(const C<float> *u, C<float> *y, const Dft16Frag &A)
 {
     bf16x8 bh, bl;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        __bf16 h, l;
-        split_bf16(u[i].x, h, l);
-        bh[2 * i] = h;
-        bl[2 * i] = l;
-        split_bf16(u[i].y, h, l);
-        bh[2 * i + 1] = h;
-        bl[2 * i + 1] = l;
-    }
+    split4_bf16(u, bh, bl);
     f32x4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
     dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.re_hi, bl, dr, 0, 0, 0);
     dr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.re_lo, bh, dr, 0, 0, 0);
@@ -53,6 +44,54 @@ __device__ __forceinline__ void twiddle4(int j, int r0, int Ns, C<float> *w)
 #pragma unroll
     for (int i = 1; i < 4; ++i)
         w[i] = cmul(w[i - 1], w1);
+}
+
+// The chirp turns of a lane's 16 positions p(q, i) = base + 16 q + 256 i
+// (group q, element i): qc n_p^2 [+ (N - 1) p / (2N)] + extra with
+// n_p = 2p - N + 1 = n0 + 32 q + 512 i, so that
+//   n_p^2 = n0^2 + 64 n0 q + 1024 q^2 + (1024 n0 + 32768 q) i + 262144 i^2.
+// The six coefficients are reduced modulo 1 from exact integers in
+// double-double (quad_turns), once per lane; per group, A_q and B_q of
+// turns = A_q + i B_q + i^2 C are formed and reduced in FP64, then rounded to
+// FP32, and the four values of the group are evaluated in FP32 (|i| <= 3:
+// about 6e-7 turns of rounding, well inside this path's 16-bit products).
+struct LaneChirp {
+    double a0, a1, a2, b0, b1;
+    float c;
+};
+__device__ __forceinline__ LaneChirp lane_chirp(double qhi, double qlo, bool with_index, int base, int N,
+                                                double inv2N, double extra)
+{
+    const Quad qq{qhi, qlo};
+    const double n0 = (double)(2 * base - N + 1);
+    LaneChirp L;
+    L.a0 = quad_turns(qq, n0 * n0) + extra;
+    L.a1 = quad_turns(qq, 64.0 * n0);
+    L.a2 = quad_turns(qq, 1024.0);
+    L.b0 = quad_turns(qq, 1024.0 * n0);
+    L.b1 = quad_turns(qq, 32768.0);
+    L.c = (float)frac_turns(quad_turns(qq, 262144.0));
+    if (with_index) {
+        L.a0 += index_turns(base, N, inv2N);
+        L.a1 += index_turns(16, N, inv2N);
+        L.b0 += index_turns(256, N, inv2N);
+    }
+    L.a0 = frac_turns(L.a0);
+    L.a1 = frac_turns(L.a1);
+    L.a2 = frac_turns(L.a2);
+    L.b0 = frac_turns(L.b0);
+    L.b1 = frac_turns(L.b1);
+    return L;
+}
+// The four chirp values of group q.
+__device__ __forceinline__ void lane_chirp4(const LaneChirp &L, int q, C<float> *w)
+{
+    const double fq = (double)q;
+    const float A = (float)frac_turns(fma(fq * fq, L.a2, fma(fq, L.a1, L.a0)));
+    const float B = (float)frac_turns(fma(fq, L.b1, L.b0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = cis_turns(__builtin_amdgcn_fractf(fmaf((float)(i * i), L.c, fmaf((float)i, B, A))));
 }
 
 template <int MODE>
@@ -107,20 +146,23 @@ __global__ __launch_bounds__(256) void k_lct_mf4096(const float2 *__restrict__ i
     }
 
     const Dft16Frag A = dft16_frag(lane);
+    // this lane's positions: b_q + 256 (4 g + i) = base + 16 q + 256 i
+    const int base = 64 * wave + n + 1024 * g;
 
     // stage 1 (Ns = 1): input chirp, butterflies, Stockham write b 16 + s
+    const LaneChirp cin = MODE == MODE_FWD ? lane_chirp(k.pre_hi, k.pre_lo, true, base, N, inv2N, 0.0)
+                                           : lane_chirp(k.post_hi, k.post_lo, true, base, N, inv2N, k.amp_turns);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int b = (4 * wave + q) * 16 + n;
-        const ThreadChirp c = MODE == MODE_FWD
-                                  ? seq_chirp(k.pre_hi, k.pre_lo, true, b + N16 * 4 * g, N16, N, inv2N)
-                                  : seq_chirp(k.post_hi, k.post_lo, true, b + N16 * 4 * g, N16, N, inv2N, k.amp_turns);
+        C<float> w[4];
+        lane_chirp4(cin, q, w);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             if constexpr (MODE == MODE_FWD)
-                u[q][i] = cmul(u[q][i], chirp_at<float>(c, i));
+                u[q][i] = cmul(u[q][i], w[i]);
             else
-                u[q][i] = cscale(cmul(cconj(u[q][i]), chirp_at<float>(c, i)), mag);
+                u[q][i] = cscale(cmul(cconj(u[q][i]), w[i]), mag);
         }
         C<float> y[4];
         mfma_dft16(u[q], y, A);
@@ -135,6 +177,8 @@ __global__ __launch_bounds__(256) void k_lct_mf4096(const float2 *__restrict__ i
 
     // stage 3 (Ns = 256): read, twiddle W_4096^(b r), butterflies, output
     // chirp, store positions b + 256 s
+    const LaneChirp cout = MODE == MODE_FWD ? lane_chirp(k.post_hi, k.post_lo, true, base, N, inv2N, k.amp_turns)
+                                            : lane_chirp(k.pre_hi, k.pre_lo, true, base, N, inv2N, 0.0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int b = (4 * wave + q) * 16 + n;
@@ -147,17 +191,16 @@ __global__ __launch_bounds__(256) void k_lct_mf4096(const float2 *__restrict__ i
         for (int i = 0; i < 4; ++i)
             x[i] = cmul(x[i], w[i]);
         mfma_dft16(x, y, A);
-        const ThreadChirp c = MODE == MODE_FWD
-                                  ? seq_chirp(k.post_hi, k.post_lo, true, b + N16 * 4 * g, N16, N, inv2N, k.amp_turns)
-                                  : seq_chirp(k.pre_hi, k.pre_lo, true, b + N16 * 4 * g, N16, N, inv2N);
+        C<float> cw[4];
+        lane_chirp4(cout, q, cw);
         const int voff = (b + N16 * 4 * g) * (int)sizeof(float2);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             C<float> o;
             if constexpr (MODE == MODE_FWD)
-                o = cscale(cmul(y[i], chirp_at<float>(c, i)), mag);
+                o = cscale(cmul(y[i], cw[i]), mag);
             else
-                o = cconj(cmul(y[i], chirp_at<float>(c, i)));
+                o = cconj(cmul(y[i], cw[i]));
             Buf<float>::store(o, rout, voff, i * N16 * (int)sizeof(float2));
         }
     }

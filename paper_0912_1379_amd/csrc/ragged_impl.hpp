@@ -122,7 +122,7 @@ __device__ __noinline__ void rag_frft_group(const RagArgs &a, const RagItem &it,
     const RagDesc d = a.desc[s];
     const float2 *src = a.in + d.offset;
     float2 *dst = a.out + d.offset;
-    const FrConst k = fr_const(N, d.p[0], d.p[1]);
+    const FrConst k = fr_const(N, d.p[0], d.p[1], false);
     CF *lds = smem + (size_t)sl * lds_elems(L);
     if (k.special) {
 #pragma unroll
@@ -132,23 +132,25 @@ __device__ __noinline__ void rag_frft_group(const RagArgs &a, const RagItem &it,
                 stc<float>(dst + j, cscale(ldc<float>(src + (k.special == 1 ? j : N - 1 - j)), (float)k.cre));
         }
     }
+    // kernel at m = p = t + T e up to N, m = L - p = (L - t) - T e beyond;
+    // data chirp at n_p = 2p - N + 1 = (2t - N + 1) + 2T e (E is even)
     CF K[E];
+    {
+        const GaussPoly lo = gauss_poly(k.kmag, k.kph_hi, k.kph_lo, t, T);
+        const GaussPoly hi = gauss_poly(k.kmag, k.kph_hi, k.kph_lo, L - t, -T);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int p = t + T * e;
-        const int m = p <= N ? p : L - p;
-        K[e] = gauss_chirp<float>(k.kmag, k.kph_hi, k.kph_lo, (double)m * (double)m);
+        for (int e = 0; e < E; ++e)
+            K[e] = t + T * e <= N ? gauss_at(lo, e) : gauss_at(hi, e);
     }
     fft_lds<E>(K, lds, t, T, z.sc);
+    const GaussPoly dch = gauss_poly(k.dmag, k.dph_hi, k.dph_lo, 2 * t - N + 1, 2 * T);
     CF v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = t + T * e;
         CF x = {0.f, 0.f};
-        if (e < E / 2 && live && !k.special) {
-            x = ldc<float>(src + (k.hankel ? N - 1 - p : p));
-            x = cmul(x, gauss_chirp<float>(k.dmag, k.dph_hi, k.dph_lo, nsq(p, N)));
-        }
+        if (e < E / 2 && live && !k.special)
+            x = cmul(ldc<float>(src + (k.hankel ? N - 1 - p : p)), gauss_at(dch, e));
         v[e] = x;
     }
     fft_lds<E>(v, lds, t, T, z.sc);
@@ -160,7 +162,7 @@ __device__ __noinline__ void rag_frft_group(const RagArgs &a, const RagItem &it,
 #pragma unroll
         for (int e = 0; e < E / 2; ++e) {
             const int j = t + T * e;
-            CF y = cmul(cconj(v[e]), gauss_chirp<float>(k.dmag, k.dph_hi, k.dph_lo, nsq(j, N)));
+            CF y = cmul(cconj(v[e]), gauss_at(dch, e));
             stc<float>(dst + j, cmul(y, CF{(float)k.cre, (float)k.cim}));
         }
     }
@@ -312,9 +314,10 @@ __device__ __forceinline__ void rag_icols(const RagSize &z, CF *smem, const floa
             lds[lds_pad(t + T1 * e)] = v[e];
         __syncthreads();
         if (n20 + sl2 < N2) {
+            store.begin(n20 + sl2 + N2 * t2, N2 * T1);
 #pragma unroll
             for (int e = 0; e < E1; ++e)
-                store(n20 + sl2 + N2 * (t2 + T1 * e), l2[lds_pad(t2 + T1 * e)]);
+                store(n20 + sl2 + N2 * (t2 + T1 * e), l2[lds_pad(t2 + T1 * e)], e);
         }
     }
     __syncthreads();
@@ -349,36 +352,41 @@ struct PostChirpStore { // post-chirped outputs at k2 N1 + k1
 struct GaussData { // e^{-P x_i^2} f_i (reversed for the Hankel form), zero beyond N
     const float2 *src;
     FrConst k;
-    int N;
-    __device__ void begin(int, int) {}
-    __device__ CF operator()(int i, int) const
+    int N, N2, T1;
+    GaussPoly g;
+    // positions i = (t + T1 e) N2 + n2: n_i = 2i - N + 1 is linear in e
+    __device__ void begin(int t, int n2) { g = gauss_poly(k.dmag, k.dph_hi, k.dph_lo, 2 * (t * N2 + n2) - N + 1, 2 * T1 * N2); }
+    __device__ CF operator()(int i, int e) const
     {
         CF x = {0.f, 0.f};
-        if (i < N) {
-            x = ldc<float>(src + (k.hankel ? N - 1 - i : i));
-            x = cmul(x, gauss_chirp<float>(k.dmag, k.dph_hi, k.dph_lo, nsq(i, N)));
-        }
+        if (i < N)
+            x = cmul(ldc<float>(src + (k.hankel ? N - 1 - i : i)), gauss_at(g, e));
         return x;
     }
 };
 struct GaussKernel { // Toeplitz kernel at circular position i
     double kmag, kph_hi, kph_lo;
-    int N, L;
-    __device__ void begin(int, int) {}
-    __device__ CF operator()(int i, int) const
+    int N, L, N2, T1;
+    GaussPoly lo, hi;
+    // m = i up to N, L - i beyond; i = (t N2 + n2) + T1 N2 e
+    __device__ void begin(int t, int n2)
     {
-        const int m = i <= N ? i : L - i;
-        return gauss_chirp<float>(kmag, kph_hi, kph_lo, (double)m * (double)m);
+        lo = gauss_poly(kmag, kph_hi, kph_lo, t * N2 + n2, T1 * N2);
+        hi = gauss_poly(kmag, kph_hi, kph_lo, L - (t * N2 + n2), -T1 * N2);
     }
+    __device__ CF operator()(int i, int e) const { return i <= N ? gauss_at(lo, e) : gauss_at(hi, e); }
 };
 struct FrOutStore { // the first N outputs: conjugate, diagonal e^{-P x_j^2}, constant
     float2 *dst;
     double dmag, dph_hi, dph_lo, cre, cim;
     int N;
-    __device__ void operator()(int j, CF y) const
+    GaussPoly g;
+    // outputs j = j0 + D e: n_j = 2j - N + 1 linear in e
+    __device__ void begin(int j0, int D) { g = gauss_poly(dmag, dph_hi, dph_lo, 2 * j0 - N + 1, 2 * D); }
+    __device__ void operator()(int j, CF y, int e) const
     {
         if (j < N) {
-            CF o = cmul(cconj(y), gauss_chirp<float>(dmag, dph_hi, dph_lo, nsq(j, N)));
+            CF o = cmul(cconj(y), gauss_at(g, e));
             stc<float>(dst + j, cmul(o, CF{(float)cre, (float)cim}));
         }
     }
@@ -418,17 +426,17 @@ __device__ __noinline__ void rag_frft_big(const RagArgs &a, const RagItem &it, c
     float2 *dst = a.out + d.offset;
     float2 *R0 = a.ws + a.wsoff[s];
     float2 *R1 = R0 + L;
-    const FrConst k = fr_const(N, d.p[0], d.p[1]);
+    const FrConst k = fr_const(N, d.p[0], d.p[1], false);
     if (k.special) {
         for (int j = (int)threadIdx.x; j < N; j += RAG_THREADS)
             stc<float>(dst + j, cscale(ldc<float>(src + (k.special == 1 ? j : N - 1 - j)), (float)k.cre));
         __syncthreads();
         return;
     }
-    rag_cols<E1>(z, L, smem, R0, GaussData{src, k, N});
-    rag_cols<E1>(z, L, smem, R1, GaussKernel{k.kmag, k.kph_hi, k.kph_lo, N, L});
+    rag_cols<E1>(z, L, smem, R0, GaussData{src, k, N, z.N2, z.T1, {}});
+    rag_cols<E1>(z, L, smem, R1, GaussKernel{k.kmag, k.kph_hi, k.kph_lo, N, L, z.N2, z.T1, {}, {}});
     rag_rows_conv<E2>(z, L, smem, R0, R1);
-    rag_icols<E1>(z, smem, R0, FrOutStore{dst, k.dmag, k.dph_hi, k.dph_lo, k.cre, k.cim, N});
+    rag_icols<E1>(z, smem, R0, FrOutStore{dst, k.dmag, k.dph_hi, k.dph_lo, k.cre, k.cim, N, {}});
 }
 
 #define RAG_E_LIST(X) X(16) X(20) X(24)
