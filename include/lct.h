@@ -240,6 +240,35 @@ int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, 
                        size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Aliasing-aware discrete LCT (b != 0).  The Algorithm samples f on x_k (step
+ * h = pi / sqrt(2N)); the pre-chirp e^{i a x^2/(2b)} has local frequency
+ * |a/b| |x|, so where |a/b| |x| plus f's own bandwidth passes the grid's
+ * Nyquist limit pi / h = sqrt(2N) the sum aliases and no longer approximates
+ * the integral of §1 (at the edge |x| = x_max this happens for |a/b| > 4/pi).
+ * This mode first interpolates the samples trigonometrically onto the grid of
+ * step h / P over the same span,
+ *   f(x) = sum_n c_n e^{2 pi i n (x - x_0) / (N h)},  c_n = (1/N) sum_k f_k e^{-2 pi i n k / N},
+ * n from -N/2 to N/2 (for even N the coefficient of n = -N/2 split in halves
+ * between -N/2 and +N/2), then takes the Riemann sum of §1 on that grid (the
+ * scaled grid of lct_plan_create_scaled with P N points and s = 1 / sqrt(P),
+ * whose Nyquist limit is P times higher) and returns it at the Algorithm's
+ * output nodes y_j = 4 b x_j / pi, the middle N of its P N outputs:
+ *   out[j] = (h/P) (2 pi i b)^(-1/2) sum_m exp(i [a xi_m^2 - 2 xi_m y_j + d y_j^2]/(2b)) f(xi_m),
+ *   xi_m = (h/P)(m - (P N - 1)/2).
+ * P = 1 or b = 0 is lct_exec.  Requirements: a plan of LCT_FP32 or LCT_FP64
+ * on the Algorithm's grid (not scaled; else LCT_ERR_UNSUPPORTED), P >= 1 with
+ * (P - 1) N even (else LCT_ERR_ARG), P N of the form 2^a 3^b 5^c
+ * (LCT_ERR_UNSUPPORTED_N), within the single-pass limit (lct_max_single_pass)
+ * and with every prime factor of P dividing N (the two DFTs of the
+ * interpolation share one thread layout); else LCT_ERR_UNSUPPORTED.  ws: DEVICE, 16-byte
+ * aligned, lct_oversampled_workspace_size(N, P, prec, batch) bytes (the P N
+ * fine samples per signal; LCT_ERR_WORKSPACE if smaller).  in == out allowed.
+ */
+size_t lct_oversampled_workspace_size(int64_t N, int P, lct_precision prec, int64_t batch);
+int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t batch, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/*
  * Ragged batch in one persistent launch: signals of different lengths, each
  * an LCT with its own matrix or a same-grid fractional transform with its own
  * order.  This extends the paper's single-transform statement to a batch.

@@ -231,6 +231,24 @@ def lct_param_grad_many(f: torch.Tensor, g: torch.Tensor, M4: torch.Tensor, grad
     return grad4
 
 
+def lct_oversampled_workspace_size(N: int, P: int, precision: int, batch: int) -> int:
+    return int(_lib.load().lct_oversampled_workspace_size(int(N), int(P), int(precision), int(batch)))
+
+
+def lct_exec_oversampled(plan: Plan, P: int, x: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
+    """Aliasing-aware LCT: the samples interpolated onto the grid P times finer,
+    the Riemann sum taken there, returned at the Algorithm's output nodes."""
+    batch, out = _plan_io(plan, x, out)
+    need = lct_oversampled_workspace_size(plan.N, P, plan.precision, batch)
+    if ws is None:
+        ws = _workspace(need, x.device)
+    rc = _lib.load().lct_exec_oversampled(plan.handle, int(P), x.data_ptr(), out.data_ptr(), batch,
+                                          None if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
+                                          _stream_handle(stream))
+    _lib.check(rc, "lct_exec_oversampled")
+    return out
+
+
 def frft_workspace_size(N: int, precision: int, batch: int) -> int:
     return int(_lib.load().frft_workspace_size(int(N), int(precision), int(batch)))
 

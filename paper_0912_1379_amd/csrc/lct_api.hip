@@ -578,6 +578,82 @@ int frft_exec_noalloc(lct_plan p, double z_re, double z_im, const void *in, void
     return frft_run(p->N, p->prec == LCT_FP64, nullptr, &k, in, out, batch, ws, need, stream);
 }
 
+size_t lct_oversampled_workspace_size(int64_t N, int P, lct_precision prec, int64_t batch)
+{
+    if (!smooth235(N) || P < 1 || batch < 0 || (prec != LCT_FP32 && prec != LCT_FP64))
+        return 0;
+    return (size_t)batch * (size_t)P * (size_t)N * (prec == LCT_FP64 ? 16 : 8);
+}
+
+int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t batch, void *ws, size_t ws_bytes,
+                         hipStream_t stream)
+{
+    if (!p || P < 1 || batch < 0)
+        return LCT_ERR_ARG;
+    if (p->prec == LCT_FP32_SPLITBF16 || p->s != 1.0)
+        return LCT_ERR_UNSUPPORTED;
+    // no aliasing to remove: the diagonal (b = 0), or the plain grid
+    if (P == 1 || p->b == 0.0)
+        return lct_exec(p, in, out, batch, stream);
+    const int64_t N = p->N, M = (int64_t)P * N;
+    if (((int64_t)(P - 1) * N) % 2 != 0)
+        return LCT_ERR_ARG; // the y_j would fall between the fine output nodes
+    const bool fp64 = p->prec == LCT_FP64;
+    if (!smooth235(M))
+        return LCT_ERR_UNSUPPORTED_N;
+    if (M > single_pass_limit(fp64))
+        return LCT_ERR_UNSUPPORTED;
+    for (int q : {2, 3, 5})
+        if (P % q == 0 && N % q != 0)
+            return LCT_ERR_UNSUPPORTED; // the two DFTs share one thread layout
+    if (batch == 0)
+        return LCT_OK;
+    int rc;
+    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
+        return rc;
+    const size_t need = (size_t)batch * (size_t)M * (fp64 ? 16 : 8);
+    if (ws == nullptr || ws_bytes < need || ((uintptr_t)ws) % 16)
+        return LCT_ERR_WORKSPACE;
+    if (batch > INT32_MAX)
+        return LCT_ERR_ARG;
+    // values per thread: E divides N (and so P N), schedules with radices
+    // dividing E exist for both lengths, at most 1024 threads
+    InterpArgs a{};
+    int E = 0;
+    for (int cand : {16, 20, 24, 12, 10, 8, 15, 6, 5, 4, 3, 2}) {
+        if (N % cand || M / cand > 1024 || !interp_width_ok(cand))
+            continue;
+        const Sched s1 = greedy_sched(N, cand, 16, false), s2 = greedy_sched(M, cand, 16, false);
+        if (s1.nst < 0 || s2.nst < 0)
+            continue;
+        E = cand;
+        a.sc1 = s1;
+        a.sc2 = s2;
+        break;
+    }
+    if (E == 0)
+        return LCT_ERR_UNSUPPORTED;
+    a.N = (int)N;
+    a.P = P;
+    a.T = (int)(M / E);
+    a.T1 = (int)(N / E);
+    a.batch = batch;
+    const size_t lds = (size_t)lds_elems((int)M) * (fp64 ? 16 : 8);
+    if (lds > LDS_BYTES)
+        return LCT_ERR_UNSUPPORTED;
+    if ((rc = hip_status(launch_interp(fp64, E, in, ws, a, lds, stream))))
+        return rc;
+    // the fine grid is the scaled grid s x'_m of M points, s = 1 / sqrt(P):
+    // step h / P over the same span; its outputs 4 b x'_m / (pi s) hold the
+    // Algorithm's y_j at m = j + (P - 1) N / 2
+    const LctConst k = lct_const_scaled(M, p->a, p->b, p->c, p->d, 1.0 / sqrt((double)P));
+    if (!lct_const_finite(k))
+        return LCT_ERR_ARG;
+    if ((rc = lct_run(M, fp64, false, nullptr, &k, 0, ws, ws, batch, stream)))
+        return rc;
+    return hip_status(launch_window(fp64, ws, out, (int)N, (int)M, (int)((P - 1) * N / 2), batch, stream));
+}
+
 int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im,
                        double d_re, double d_im, const void *in, void *out, int64_t batch, void *ws,
                        size_t ws_bytes, hipStream_t stream)

@@ -128,4 +128,17 @@ LCTK_DISPATCH_DECL(f32)
 LCTK_DISPATCH_DECL(f64)
 #undef LCTK_DISPATCH_DECL
 
+// Aliasing-aware LCT: trigonometric interpolation onto the grid P times finer
+// (one work-group of T = P N / E threads per signal) and the window copy.
+struct InterpArgs {
+    int N, P;       // samples, oversampling factor (fine length P N)
+    int T;          // threads per work-group: P N / E
+    int T1;         // threads of the length-N DFT: N / E (<= T)
+    int64_t batch;
+    Sched sc1, sc2; // schedules of the length-N and length-P N DFTs
+};
+bool interp_width_ok(int E);
+hipError_t launch_interp(bool fp64, int E, const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s);
+hipError_t launch_window(bool fp64, const void *fine, void *out, int N, int M, int off, int64_t batch, hipStream_t s);
+
 } // namespace lctk

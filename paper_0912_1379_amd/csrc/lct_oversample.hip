@@ -1,0 +1,59 @@
+// lct_oversample.hip - launches of the aliasing-aware LCT's own kernels (the
+// interpolation onto the finer grid and the window copy); the fine-grid
+// transform itself runs on the LCT kernels.
+#include "oversample_impl.hpp"
+
+namespace lctk {
+
+namespace {
+template <typename R>
+hipError_t launch_interp_t(int E, const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s)
+{
+    using V = typename Vec<R>::T;
+    switch (E) {
+#define X(e)                                                                                                         \
+    case e: {                                                                                                        \
+        if (hipError_t r = allow_lds((const void *)k_interp<R, e>, lds); r != hipSuccess)                             \
+            return r;                                                                                                \
+        hipLaunchKernelGGL((k_interp<R, e>), dim3((unsigned)a.batch), dim3(a.T), lds, s, (const V *)in, (V *)ws, a);  \
+        return hipGetLastError();                                                                                    \
+    }
+        X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+} // namespace
+
+bool interp_width_ok(int E)
+{
+    switch (E) {
+    case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 15: case 16: case 20: case 24:
+        return true;
+    default:
+        return false;
+    }
+}
+
+hipError_t launch_interp(bool fp64, int E, const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s)
+{
+    return fp64 ? launch_interp_t<double>(E, in, ws, a, lds, s) : launch_interp_t<float>(E, in, ws, a, lds, s);
+}
+
+hipError_t launch_window(bool fp64, const void *fine, void *out, int N, int M, int off, int64_t batch, hipStream_t s)
+{
+    const int64_t total = batch * N;
+    const int bs = 256;
+    const int64_t want = (total + bs - 1) / bs;
+    const unsigned nb = (unsigned)(want < 65536 ? want : 65536);
+    if (fp64)
+        hipLaunchKernelGGL(k_window<double>, dim3(nb), dim3(bs), 0, s, (const double2 *)fine, (double2 *)out, N, M,
+                           off, total);
+    else
+        hipLaunchKernelGGL(k_window<float>, dim3(nb), dim3(bs), 0, s, (const float2 *)fine, (float2 *)out, N, M, off,
+                           total);
+    return hipGetLastError();
+}
+
+} // namespace lctk

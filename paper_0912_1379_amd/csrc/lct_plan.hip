@@ -70,36 +70,6 @@ bool sched_valid(const Sched &sc, int64_t Nfft, int E)
 
 // Greedy schedule over the allowed radices (largest first); `rev` runs the
 // same stages in the opposite order.
-Sched greedy_sched(int64_t N, int E, int maxrad, bool rev)
-{
-    Sched s{};
-    int64_t rem = N;
-    while (rem > 1 && s.nst < 24) {
-        bool ok = false;
-        for (int c : RADICES) {
-            if (c <= maxrad && E % c == 0 && rem % c == 0) {
-                s.rad[s.nst++] = c;
-                rem /= c;
-                ok = true;
-                break;
-            }
-        }
-        if (!ok)
-            break;
-    }
-    if (rem != 1) {
-        s.nst = -1;
-        return s;
-    }
-    if (rev)
-        for (int i = 0, j = s.nst - 1; i < j; ++i, --j) {
-            const int x = s.rad[i];
-            s.rad[i] = s.rad[j];
-            s.rad[j] = x;
-        }
-    return s;
-}
-
 bool same_sched(const Sched &a, const Sched &b)
 {
     if (a.nst != b.nst)
@@ -170,6 +140,38 @@ int pick_group(int Nsub, int T, int E, int other, bool fp64, int cap_limit)
 }
 
 } // namespace
+
+Sched greedy_sched(int64_t N, int E, int maxrad, bool rev)
+{
+    Sched s{};
+    int64_t rem = N;
+    while (rem > 1 && s.nst < 24) {
+        bool ok = false;
+        for (int c : {16, 8, 5, 4, 3, 2}) {
+            if (c <= maxrad && E % c == 0 && rem % c == 0) {
+                s.rad[s.nst++] = c;
+                rem /= c;
+                ok = true;
+                break;
+            }
+        }
+        if (!ok)
+            break;
+    }
+    if (rem != 1) {
+        s.nst = -1;
+        return s;
+    }
+    if (rev)
+        for (int i = 0, j = s.nst - 1; i < j; ++i, --j) {
+            const int x = s.rad[i];
+            s.rad[i] = s.rad[j];
+            s.rad[j] = x;
+        }
+    return s;
+}
+
+
 
 Tiling tiling_of(int64_t Nfft, bool fp64, int E, int S, const Sched &sc, size_t extra)
 {

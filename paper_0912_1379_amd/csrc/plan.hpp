@@ -40,6 +40,10 @@ int64_t single_pass_limit(bool fp64);
 Tiling tiling_of(int64_t Nfft, bool fp64, int E, int S, const Sched &sc, size_t extra);
 FsTiling fs_of(int64_t N, bool fp64, int N1, int E1, int E2, int C, int RR, const Sched &sc1, const Sched &sc2);
 
+// Greedy radix schedule of a length-N DFT with E values per thread (largest
+// radix first, radices <= maxrad dividing E); nst = -1 if none exists.
+Sched greedy_sched(int64_t N, int E, int maxrad, bool rev);
+
 // Built-in heuristic choices.
 Tiling default_tiling(int64_t Nfft, bool fp64, bool frft, size_t extra);
 FsTiling default_fs(int64_t N, bool fp64, bool frft = false);
