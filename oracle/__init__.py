@@ -32,6 +32,11 @@ Functions and what pins them (the pins live in ``tests/test_oracle_*.py``):
                             grid at the Algorithm's output nodes; pinned by
                             p = 1 (O1), the chirped-Gaussian closed form where
                             O1 aliases, and the explicit interpolation sum.
+``lct_complex(f, a, b, d)`` LCT of §1 for a complex matrix at the Algorithm's
+                            complex output nodes 4 b x_j / pi (O6; the bilateral
+                            Laplace transform for (0, i, 0)); pinned by O1 for
+                            real matrices, the complex Gaussian integral, the
+                            Laplace transform of a Gaussian and mpmath.
 ``lct_adjoint``             conjugate transpose of the same matrix; pinned by
                             the inner-product identity and unitarity.
 ``lct_param_grad``          derivative of the dense matrix w.r.t. (a,b,c,d)
@@ -86,6 +91,8 @@ def _load():
     lib.oracle_lct_rows_scaled.argtypes = [i64, d, d, d, d, d, _dp, _i64p, i64, _dp]
     lib.oracle_lct_rows_scaled.restype = ctypes.c_int
     lib.oracle_lct_same_rows.argtypes = [i64, d, d, d, d, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_lct_complex_rows.argtypes = [i64, d, d, d, d, d, d, _dp, _i64p, i64, _dp]
+    lib.oracle_lct_complex_rows.restype = ctypes.c_int
     lib.oracle_lct_same_rows.restype = ctypes.c_int
     lib.oracle_lct_adjoint.argtypes = [i64, d, d, d, d, _dp, _dp]
     lib.oracle_lct_adjoint.restype = ctypes.c_int
@@ -237,6 +244,34 @@ def lct_same_grid(f, a: complex, b: complex, d: complex, rows=None) -> np.ndarra
                                       _ptr(out.view(np.float64)))
     if rc != 0:
         raise ValueError(f"oracle_lct_same_rows failed ({rc})")
+    return out
+
+
+def complex_output_nodes(N: int, b: complex) -> np.ndarray:
+    """The Algorithm's output nodes y_j = 4 b x_j / pi for a complex b."""
+    return 4.0 * complex(b) * nodes(N) / np.pi
+
+
+def lct_complex(f, a: complex, b: complex, d: complex, rows=None) -> np.ndarray:
+    """LCT of §1 for a complex matrix (O6): the Riemann sum on the input nodes
+    x_k at the complex output nodes y_j = 4 b x_j / pi; 1-D f.  (0, i, 0) is
+    the bilateral Laplace transform (times (-2 pi)^(-1/2)) on the imaginary
+    axis."""
+    f = _cplx_in(f)
+    N = f.shape[0]
+    if rows is None:
+        r = None
+        nr = N
+    else:
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr = r.shape[0]
+    a, b, d = complex(a), complex(b), complex(d)
+    out = np.empty(nr, dtype=np.complex128)
+    rc = _load().oracle_lct_complex_rows(N, a.real, a.imag, b.real, b.imag, d.real, d.imag,
+                                         _ptr(f.view(np.float64)), None if r is None else r.ctypes.data_as(_i64p),
+                                         nr, _ptr(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError(f"oracle_lct_complex_rows failed ({rc})")
     return out
 
 

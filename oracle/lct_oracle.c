@@ -234,6 +234,53 @@ int oracle_lct_same_rows(int64_t N, double ar, double ai, double br, double bi, 
 }
 
 /*
+ * O6: the LCT of §1 for a complex matrix (a, b, d complex, b != 0; c implied
+ * by ad - bc = 1) as the Riemann sum of its integral on the Algorithm's input
+ * nodes x_k (eq. asymcer) at its output nodes y_j = 4 b x_j / pi, here complex:
+ *   G_j = sum_k h (2 pi i b)^(-1/2) exp(i [a x_k^2 - 2 x_k y_j + d y_j^2]/(2b)) f_k,
+ * principal branch of the root.  The bilateral Laplace transform is the case
+ * (a, b, d) = (0, i, 0): G_j = (-2 pi)^(-1/2) h sum_k e^{-x_k y_j} f_k at
+ * y_j = 4 i x_j / pi.  rows == NULL means every row (nrows must be N).
+ * Returns 0, or -1 on bad arguments.
+ * Pinned: O1 for real matrices, the complex Gaussian integral, the bilateral
+ * Laplace transform of a Gaussian in closed form, mpmath brute force.
+ */
+int oracle_lct_complex_rows(int64_t N, double ar, double ai, double br, double bi, double dr, double di,
+                            const double *f, const int64_t *rows, int64_t nrows, double *out)
+{
+    if (N < 1 || f == NULL || out == NULL || nrows < 0 || (br == 0.0 && bi == 0.0))
+        return -1;
+    if (rows == NULL && nrows != N)
+        return -1;
+    const long double h = PI_L / sqrtl(2.0L * (long double)N);
+    const long double complex A = CMPLXL(ar, ai), B = CMPLXL(br, bi), D = CMPLXL(dr, di);
+    const long double complex w = CMPLXL(0.0L, 1.0L) / (2.0L * B); /* i / (2b) */
+    const long double complex amp = h / csqrtl(CMPLXL(0.0L, 2.0L * PI_L) * B);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t j = rows ? rows[r] : r;
+        if (j < 0 || j >= N) {
+            bad = 1;
+            continue;
+        }
+        const long double complex yj = 4.0L * B * node_l(N, j) / PI_L;
+        ksum ar_ = {0.0L, 0.0L}, ai_ = {0.0L, 0.0L};
+        for (int64_t k = 0; k < N; ++k) {
+            const long double xk = node_l(N, k);
+            const long double complex e = w * (A * xk * xk - 2.0L * xk * yj + D * yj * yj);
+            const long double complex t = cexpl(e) * CMPLXL((long double)f[2 * k], (long double)f[2 * k + 1]);
+            ksum_add(&ar_, creall(t));
+            ksum_add(&ai_, cimagl(t));
+        }
+        const long double complex v = amp * CMPLXL(ksum_value(&ar_), ksum_value(&ai_));
+        out[2 * r] = (double)creall(v);
+        out[2 * r + 1] = (double)cimagl(v);
+    }
+    return bad ? -1 : 0;
+}
+
+/*
  * Adjoint of the discrete LCT matrix of oracle_lct_rows (b != 0):
  *   (L^H g)_k = sum_j conj(L_jk) g_j.
  * This is the gradient of a real loss with respect to the input samples in
