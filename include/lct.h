@@ -240,6 +240,29 @@ int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, 
                        size_t ws_bytes, hipStream_t stream);
 
 /*
+ * LCT of §1 for a complex matrix (a, b, d complex, b != 0; c follows from
+ * ad - bc = 1 and does not enter), evaluated by the Algorithm as printed with
+ * complex parameters: input on x_k, output at the complex nodes
+ * y_j = 4 b x_j / pi (lct_complex_nodes), as the Riemann sum of the integral
+ *   out[j] = h (2 pi i b)^(-1/2) sum_k exp(i [a x_k^2 - 2 x_k y_j + d y_j^2]/(2b)) in[k].
+ * The cross term -x_k y_j / b = -4 x_k x_j / pi is real for every b, so the
+ * DFT and its index phases are those of the real case; the pre- and
+ * post-diagonals become Gaussian chirps exp(i (a/b) x_k^2 / 2) and
+ * exp(i b d n_j^2 / N).  Accepted when both have modulus <= 1:
+ * Im(a/b) >= 0 and Im(b d) >= 0 (relative slack 1e-12), else
+ * LCT_ERR_DOMAIN.  The bilateral Laplace transform, the abstract's special
+ * case with kernel e^{-x y}, is (a, b, d) = (0, i, 0): out[j] =
+ * (-2 pi)^(-1/2) h sum_k e^{-x_k y_j} in[k] on the imaginary axis
+ * y_j = 4 i x_j / pi.  One matrix per call; single-pass lengths
+ * (lct_max_single_pass) else LCT_ERR_UNSUPPORTED; b = 0 and
+ * LCT_FP32_SPLITBF16 give LCT_ERR_UNSUPPORTED.  in == out allowed.
+ * lct_complex_nodes: host helper, y (HOST, 2N doubles, interleaved complex).
+ */
+int lct_complex_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im, double d_re,
+                     double d_im, const void *in, void *out, int64_t batch, hipStream_t stream);
+int lct_complex_nodes(int64_t N, double b_re, double b_im, double *y);
+
+/*
  * Aliasing-aware discrete LCT (b != 0).  The Algorithm samples f on x_k (step
  * h = pi / sqrt(2N)); the pre-chirp e^{i a x^2/(2b)} has local frequency
  * |a/b| |x|, so where |a/b| |x| plus f's own bandwidth passes the grid's

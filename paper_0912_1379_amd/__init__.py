@@ -231,6 +231,29 @@ def lct_param_grad_many(f: torch.Tensor, g: torch.Tensor, M4: torch.Tensor, grad
     return grad4
 
 
+def lct_complex_exec(x: torch.Tensor, a: complex, b: complex, d: complex, out=None, stream=None) -> torch.Tensor:
+    """LCT of a complex matrix at the Algorithm's complex output nodes 4 b x_j / pi
+    ((0, i, 0): the bilateral Laplace transform on the imaginary axis)."""
+    _check_data(x, "x")
+    N = x.shape[-1]
+    batch = _batch_of(x, N)
+    out = _out_like(x, out)
+    a, b, d = complex(a), complex(b), complex(d)
+    rc = _lib.load().lct_complex_exec(N, _prec_of(x), a.real, a.imag, b.real, b.imag, d.real, d.imag, x.data_ptr(),
+                                      out.data_ptr(), batch, _stream_handle(stream))
+    _lib.check(rc, "lct_complex_exec")
+    return out
+
+
+def lct_complex_nodes(N: int, b: complex) -> np.ndarray:
+    """Output nodes 4 b x_j / pi (complex) of lct_complex_exec."""
+    y = np.empty(2 * int(N), dtype=np.float64)
+    b = complex(b)
+    _lib.check(_lib.load().lct_complex_nodes(int(N), b.real, b.imag, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "lct_complex_nodes")
+    return y.view(np.complex128)
+
+
 def lct_oversampled_workspace_size(N: int, P: int, precision: int, batch: int) -> int:
     return int(_lib.load().lct_oversampled_workspace_size(int(N), int(P), int(precision), int(batch)))
 

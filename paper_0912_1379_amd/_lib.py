@@ -62,6 +62,8 @@ SIGNATURES = {
     "frft_exec_noalloc": (_int, [_vp, _d, _d, _vp, _vp, _i64, _vp]),
     "lct_oversampled_workspace_size": (ctypes.c_size_t, [_i64, _int, _int, _i64]),
     "lct_exec_oversampled": (_int, [_vp, _int, _vp, _vp, _i64, _vp, ctypes.c_size_t, _vp]),
+    "lct_complex_exec": (_int, [_i64, _int, _d, _d, _d, _d, _d, _d, _vp, _vp, _i64, _vp]),
+    "lct_complex_nodes": (_int, [_i64, _d, _d, _dp]),
     "lct_same_grid_exec": (_int, [_i64, _int, _d, _d, _d, _d, _d, _d, _vp, _vp, _i64, _vp, ctypes.c_size_t, _vp]),
     "lct_ragged_plan_create": (_int, [ctypes.POINTER(_vp), _vp, _i64, _int]),
     "lct_ragged_workspace_size": (ctypes.c_size_t, [_vp]),

@@ -1,0 +1,79 @@
+// cx_impl.hpp - the LCT of §1 for a complex matrix (a, b, d) evaluated by the
+// Algorithm as printed, with complex parameters: the cross term
+// -x_k y_j / b = -4 x_k x_j / pi does not depend on b, so the DFT and its index
+// phases are those of the real case, and only the diagonals change:
+//   pre  e^{i a x_k^2 / (2b)}    = exp(w_a x_k^2),  w_a = i a / (2b)
+//   post e^{i d y_j^2 / (2b)}    = exp(w_d x_j^2),  w_d = 8 i b d / pi^2   (y_j = 4 b x_j / pi)
+//   amp  h (2 pi i b)^(-1/2) e^{-i pi (N-1)^2 / (2N)}
+// Gaussian-chirp diagonals (modulus <= 1 when Im(a/b) >= 0 and Im(bd) >= 0).
+// The outputs sit at the complex nodes y_j = 4 b x_j / pi; (0, i, 0) is the
+// bilateral Laplace transform on the imaginary axis.
+#pragma once
+#include "kernels_impl.hpp"
+
+namespace lctk {
+
+// The diagonal exp(w n^2) (n = 2p - N + 1) times the index phase
+// (N - 1) p / (2N) at this thread's positions p = t + T e.
+template <typename R> struct CxDiag;
+template <> struct CxDiag<float> {
+    GaussPoly g;
+    __device__ CxDiag(double mag, double hi, double lo, int t, int T, int N, double inv2N)
+        : g(gauss_poly(mag, hi, lo, 2 * t - N + 1, 2 * T))
+    {
+        g.ph.A = frac_turns(g.ph.A + index_turns(t, N, inv2N));
+        g.ph.B = frac_turns(g.ph.B + index_turns(T, N, inv2N));
+    }
+    __device__ __forceinline__ C<float> at(int e) const { return gauss_at(g, e); }
+};
+template <> struct CxDiag<double> {
+    GaussPoly g;
+    __device__ CxDiag(double mag, double hi, double lo, int t, int T, int N, double inv2N)
+        : g(gauss_poly(mag, hi, lo, 2 * t - N + 1, 2 * T))
+    {
+        g.ph.A = frac_turns(g.ph.A + index_turns(t, N, inv2N));
+        g.ph.B = frac_turns(g.ph.B + index_turns(T, N, inv2N));
+    }
+    __device__ __forceinline__ C<double> at(int e) const
+    {
+        const double fe = (double)e;
+        const double u = fma(g.ph.B, fe, fma(g.ph.C, fe * fe, g.ph.A));
+        return cscale(cis_turns(frac_turns(u)), exp(fmax(gauss_logmod(g, e), -1000.0)));
+    }
+};
+
+template <typename R, int E>
+__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_cx(
+    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, CxArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
+    const int N = a.N, T = a.T;
+    const int sl = (int)threadIdx.x / T;
+    const int t = (int)threadIdx.x - sl * T;
+    const int64_t sig = (int64_t)blockIdx.x * a.S + sl;
+    const bool live = sig < a.batch;
+    const double inv2N = 0.5 / (double)N;
+    const typename Vec<R>::T *src = in + (size_t)(live ? sig : 0) * N;
+    typename Vec<R>::T *dst = out + (size_t)(live ? sig : 0) * N;
+    C<R> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = live ? ldc<R>(src + t + T * e) : C<R>{(R)0, (R)0};
+    {
+        const CxDiag<R> pre(a.k.pre_mag, a.k.pre_hi, a.k.pre_lo, t, T, N, inv2N);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = cmul(v[e], pre.at(e));
+    }
+    fft_lds<E>(v, smem + (size_t)sl * lds_elems(N), t, T, a.sc);
+    if (live) {
+        const CxDiag<R> post(a.k.post_mag, a.k.post_hi, a.k.post_lo, t, T, N, inv2N);
+        const C<R> amp{(R)a.k.amp_re, (R)a.k.amp_im};
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            stc<R>(dst + t + T * e, cmul(cmul(v[e], post.at(e)), amp));
+    }
+}
+
+} // namespace lctk

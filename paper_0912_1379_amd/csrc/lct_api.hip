@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <complex>
 #include <mutex>
 #include <new>
 
@@ -183,6 +184,44 @@ int same_grid_const(int64_t N, double ar, double ai, double br, double bi, doubl
     const double h = PI_HI / sqrt(2.0 * n);
     k->cre = h * qr / (2.0 * n);
     k->cim = h * qi / (2.0 * n);
+    return LCT_OK;
+}
+
+// Constants of the complex-matrix LCT at the complex nodes y_j = 4 b x_j / pi
+// (cx_impl.hpp).  With x^2 = pi^2 n^2 / (8N):
+//   pre  exp(i a x^2/(2b)):  log-modulus -Im(a/b) pi^2 / (16N), turns Re(a/b) pi / (32N) per n^2
+//   post exp(i d y^2/(2b)) = exp(i b d n^2 / N):  log-modulus -Im(bd) / N, turns Re(bd) / (2 pi N)
+//   amp  h (2 pi i b)^(-1/2) e^{-i pi (N-1)^2 / (2N)}  (principal root)
+// a/b and bd in double-double (their parts multiply n^2).  Both diagonals
+// must have modulus <= 1: Im(a/b) >= 0 and Im(bd) >= 0 (relative slack
+// 1e-12), else LCT_ERR_DOMAIN.
+int cx_const(int64_t N, double ar, double ai, double br, double bi, double dr, double di, CxConst *k)
+{
+    const CDD A = cdd_of(ar, ai), B = cdd_of(br, bi), D = cdd_of(dr, di);
+    const CDD ab = cdd_div(A, B), bd = cdd_mul(B, D);
+    if (ab.im.hi < -1e-12 * fmax(1.0, fabs(ab.re.hi)) || bd.im.hi < -1e-12 * fmax(1.0, fabs(bd.re.hi)))
+        return LCT_ERR_DOMAIN;
+    const double n = (double)N;
+    *k = CxConst{};
+    k->pre_mag = -fmax(ab.im.hi, 0.0) * PI_HI * PI_HI / (16.0 * n);
+    DD t = dd_div_d(dd_mul(DD{PI_HI, PI_LO}, ab.re), 32.0 * n);
+    k->pre_hi = t.hi;
+    k->pre_lo = t.lo;
+    k->post_mag = -fmax(bd.im.hi, 0.0) / n;
+    t = dd_div_d(dd_mul(bd.re, DD{INV2PI_HI, INV2PI_LO}), n);
+    k->post_hi = t.hi;
+    k->post_lo = t.lo;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double h = pi / sqrtl(2.0L * (long double)N);
+    using cld = std::complex<long double>;
+    const cld root = std::sqrt(cld(0.0L, 2.0L * pi) * cld((long double)br, (long double)bi)); // principal
+    const int64_t m = (N - 1) * (N - 1) % (4 * N);
+    const cld amp = h / root * std::exp(cld(0.0L, -pi * (long double)m / (2.0L * (long double)N)));
+    k->amp_re = (double)amp.real();
+    k->amp_im = (double)amp.imag();
+    if (!isfinite(k->pre_mag) || !isfinite(k->pre_hi) || !isfinite(k->post_mag) || !isfinite(k->post_hi) ||
+        !isfinite(k->amp_re) || !isfinite(k->amp_im))
+        return LCT_ERR_ARG;
     return LCT_OK;
 }
 
@@ -652,6 +691,61 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
     if ((rc = lct_run(M, fp64, false, nullptr, &k, 0, ws, ws, batch, stream)))
         return rc;
     return hip_status(launch_window(fp64, ws, out, (int)N, (int)M, (int)((P - 1) * N / 2), batch, stream));
+}
+
+int lct_complex_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im, double d_re,
+                     double d_im, const void *in, void *out, int64_t batch, hipStream_t stream)
+{
+    if (prec == LCT_FP32_SPLITBF16)
+        return LCT_ERR_UNSUPPORTED;
+    if (prec != LCT_FP32 && prec != LCT_FP64)
+        return LCT_ERR_ARG;
+    for (double v : {a_re, a_im, b_re, b_im, d_re, d_im})
+        if (!isfinite(v))
+            return LCT_ERR_ARG;
+    if (b_re == 0.0 && b_im == 0.0)
+        return LCT_ERR_UNSUPPORTED; // the b = 0 diagonal samples f at d y_j, off the grid for complex d
+    if (!smooth235(N))
+        return LCT_ERR_UNSUPPORTED_N;
+    const bool fp64 = prec == LCT_FP64;
+    if (N > single_pass_limit(fp64))
+        return LCT_ERR_UNSUPPORTED;
+    CxArgs a{};
+    if (int rc = cx_const(N, a_re, a_im, b_re, b_im, d_re, d_im, &a.k))
+        return rc;
+    if (batch < 0)
+        return LCT_ERR_ARG;
+    if (batch == 0)
+        return LCT_OK;
+    int rc;
+    if ((rc = check_ptr(in, fp64)) || (rc = check_ptr(out, fp64)))
+        return rc;
+    const Tiling tl = default_tiling(N, fp64, false, 0);
+    if (!tl.ok)
+        return LCT_ERR_UNSUPPORTED;
+    a.N = (int)N;
+    a.T = tl.T;
+    a.S = tl.S;
+    a.batch = batch;
+    a.sc = tl.sc;
+    const int64_t nb = (batch + tl.S - 1) / tl.S;
+    if (nb > INT32_MAX)
+        return LCT_ERR_ARG;
+    return hip_status(launch_cx(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, stream));
+}
+
+int lct_complex_nodes(int64_t N, double b_re, double b_im, double *y)
+{
+    if (N < 1 || y == nullptr || (b_re == 0.0 && b_im == 0.0) || !isfinite(b_re) || !isfinite(b_im))
+        return LCT_ERR_ARG;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double s = 4.0L / pi * (pi / (2.0L * sqrtl(2.0L * (long double)N)));
+    for (int64_t j = 0; j < N; ++j) {
+        const long double x = s * (long double)(2 * j - N + 1);
+        y[2 * j] = (double)(x * (long double)b_re);
+        y[2 * j + 1] = (double)(x * (long double)b_im);
+    }
+    return LCT_OK;
 }
 
 int lct_same_grid_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im,

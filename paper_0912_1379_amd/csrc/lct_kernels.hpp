@@ -138,6 +138,23 @@ struct InterpArgs {
     Sched sc1, sc2; // schedules of the length-N and length-P N DFTs
 };
 bool interp_width_ok(int E);
+
+// LCT of a complex matrix at the Algorithm's complex output nodes: per-n^2
+// log-modulus and turns (double-double) of the pre- and post-diagonals, and
+// the amplitude.
+struct CxConst {
+    double pre_mag, pre_hi, pre_lo;
+    double post_mag, post_hi, post_lo;
+    double amp_re, amp_im;
+};
+struct CxArgs {
+    int N, T, S;
+    int64_t batch;
+    CxConst k;
+    Sched sc;
+};
+hipError_t launch_cx(bool fp64, int E, const void *in, void *out, const CxArgs &a, int nb, int bs, size_t lds,
+                     hipStream_t s);
 hipError_t launch_interp(bool fp64, int E, const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s);
 hipError_t launch_window(bool fp64, const void *fine, void *out, int N, int M, int off, int64_t batch, hipStream_t s);
 

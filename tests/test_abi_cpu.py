@@ -417,3 +417,42 @@ def test_same_grid_domain_inequalities(lib):
     assert _same_grid_rc(lib, 0.5 - 0.3j, 1.0, 0.5) == dom
     # the bilateral Laplace matrix (0, i, i, 0): neither form
     assert _same_grid_rc(lib, 0.0, 1j, 0.0) == dom
+
+
+def _complex_rc(lib, a, b, d, N=64, prec=0):
+    a, b, d = complex(a), complex(b), complex(d)
+    return lib.lct_complex_exec(N, prec, a.real, a.imag, b.real, b.imag, d.real, d.imag, None, None, 0, None)
+
+
+def test_complex_node_lct_domain_and_arguments(lib):
+    """LCT of a complex matrix at the complex nodes 4 b x_j / pi: accepted where both
+    Gaussian-chirp diagonals are bounded (Im(a/b) >= 0, Im(b d) >= 0); b = 0,
+    split-BF16 and lengths beyond one pass are unsupported."""
+    ok, dom = _lib.LCT_OK, _lib.LCT_ERR_DOMAIN
+    assert _complex_rc(lib, 0.0, 1j, 0.0) == ok                     # bilateral Laplace
+    assert _complex_rc(lib, 0.5, 1.0, -0.5) == ok                   # real matrix
+    assert _complex_rc(lib, 0.9 + 0.1j, 0.6 - 0.2j, 1.1 + 0.5j) == ok
+    b = 0.6 - 0.2j
+    assert np.imag((0.9 - 0.6j) / b) < 0
+    assert _complex_rc(lib, 0.9 - 0.6j, b, 1.1 + 0.5j) == dom       # Im(a/b) < 0
+    assert np.imag(b * (1.1 - 0.5j)) < 0
+    assert _complex_rc(lib, 0.9 + 0.1j, b, 1.1 - 0.5j) == dom       # Im(b d) < 0
+    # the boundary Im(a/b) = 0 (a a real multiple of b) and just beyond it
+    assert _complex_rc(lib, 0.7 * b, b, 0.0) == ok
+    assert _complex_rc(lib, 0.7 * b - 1e-6j * b, b, 0.0) == dom
+    assert _complex_rc(lib, 1.0, 0.0, 1.0) == _lib.LCT_ERR_UNSUPPORTED
+    assert _complex_rc(lib, 0.0, 1j, 0.0, prec=2) == _lib.LCT_ERR_UNSUPPORTED
+    assert _complex_rc(lib, 0.0, 1j, 0.0, N=1 << 20) == _lib.LCT_ERR_UNSUPPORTED
+    assert _complex_rc(lib, 0.0, 1j, 0.0, N=7 * 64) == _lib.LCT_ERR_UNSUPPORTED_N
+    assert _complex_rc(lib, float("nan"), 1j, 0.0) == _lib.LCT_ERR_ARG
+
+
+def test_complex_nodes_helper(lib):
+    """lct_complex_nodes returns 4 b x_j / pi with x_j = h (2j - N + 1)/2, h = pi / sqrt(2N)."""
+    N, b = 10, 0.3 - 1.2j
+    y = np.empty(2 * N)
+    assert lib.lct_complex_nodes(N, b.real, b.imag, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == _lib.LCT_OK
+    h = np.pi / np.sqrt(2 * N)
+    x = h * (2 * np.arange(N) - N + 1) / 2
+    assert np.allclose(y.view(np.complex128), 4 * b * x / np.pi, rtol=1e-15, atol=1e-15)
+    assert lib.lct_complex_nodes(N, 0.0, 0.0, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == _lib.LCT_ERR_ARG
