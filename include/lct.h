@@ -53,7 +53,14 @@ enum {
     LCT_ERR_UNSUPPORTED = -7     /* valid request this build does not run */
 };
 
-typedef enum {
+/* Precision selector.  Entry points take any int-sized value here and reject
+ * the ones not listed with LCT_ERR_ARG; C++ callers see a fixed underlying
+ * type so that such values are representable. */
+typedef enum
+#ifdef __cplusplus
+    : int
+#endif
+{
     LCT_FP32 = 0,          /* complex64 data, FP32 FFT, FP64 phase reduction */
     LCT_FP64 = 1,          /* complex128 data, FP64 throughout */
     LCT_FP32_SPLITBF16 = 2 /* complex64 data; the FFT's radix-16 stages run on the
@@ -393,8 +400,22 @@ int lct_check_desc(const lct_desc *d_desc, int64_t nsig, int64_t *status, hipStr
  *   lct_tune_get         the line in use for (kind, N, precision) (host)
  *   lct_tune_set         records one line (host)
  *   lct_tune_load/save   reads / writes a file of lines ('#' comments); a file
- *                        with any invalid line is rejected as a whole
+ *                        with any invalid line (or a line over 511 bytes) is
+ *                        rejected as a whole; a field given twice is invalid
  *   lct_tune_clear       empties the table
+ *
+ * Environment (read at each use):
+ *   LCT_TUNE_CACHE=path  the table is loaded from `path` before the first
+ *                        lookup (and again if the variable changes); a
+ *                        missing or invalid file leaves the table unchanged.
+ *                        Every successful lct_autotune writes the whole table
+ *                        back (to a temporary file renamed over `path`).
+ *   LCT_AUTOTUNE=1       plan creation (FP32 and FP64 plans) runs
+ *                        lct_autotune for both transforms of the plan's
+ *                        length on the default stream with batch 0 unless the
+ *                        table already holds them; plan creation then
+ *                        allocates, synchronises and takes up to seconds.  A
+ *                        failed autotune leaves the heuristic.
  */
 enum { LCT_TUNE_LCT = 0, LCT_TUNE_FRFT = 1 };
 typedef struct {

@@ -79,11 +79,14 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIBPATH) or (
-            os.path.getmtime(_LIBPATH) < os.path.getmtime(os.path.join(_HERE, "lct_oracle.c"))):
-        from . import build as _b
-        _b.build()
-    lib = ctypes.CDLL(_LIBPATH)
+    path = os.environ.get("LCT_ORACLE_LIBRARY")  # e.g. the sanitized build of build.py --sanitize
+    if not path:
+        path = _LIBPATH
+        if not os.path.exists(path) or (
+                os.path.getmtime(path) < os.path.getmtime(os.path.join(_HERE, "lct_oracle.c"))):
+            from . import build as _b
+            _b.build()
+    lib = ctypes.CDLL(path)
     i64, d = ctypes.c_int64, ctypes.c_double
     lib.oracle_nodes.argtypes = [i64, _dp]
     lib.oracle_lct_rows.argtypes = [i64, d, d, d, d, _dp, _i64p, i64, _dp]

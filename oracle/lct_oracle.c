@@ -38,6 +38,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* glibc defines CMPLXL only for GCC; clang (the sanitized build) has the same builtin. */
+#ifndef CMPLXL
+#define CMPLXL(x, y) __builtin_complex((long double)(x), (long double)(y))
+#endif
+
 #define PI_L 3.141592653589793238462643383279502884L
 
 /* Compensated (Neumaier) summation in long double: the running sum s and the

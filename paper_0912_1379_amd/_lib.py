@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "liblct_mi355x.so")
+# LCT_LIBRARY names another build of the same ABI (the host-only sanitized
+# library of build.py --sanitize, for the CPU suite); unset, the in-tree library.
+LIBPATH = os.environ.get("LCT_LIBRARY") or os.path.join(HERE, "liblct_mi355x.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lct.h")
 
 LCT_OK = 0

@@ -454,6 +454,7 @@ int lct_plan_create_ex(lct_plan *out, int64_t N, double a, double b, double c, d
     p->d = d;
     p->s = 1.0;
     p->k = lct_const(N, a, b, c, d);
+    autotune_on_plan(N, (int)prec);
     *out = p;
     return LCT_OK;
 }

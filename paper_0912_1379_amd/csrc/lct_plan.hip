@@ -5,7 +5,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <map>
@@ -513,6 +515,10 @@ int parse_entry(const char *line, TuneKey *key, TuneEntry *ent)
     }
     if (kind != "lct" && kind != "frft")
         return LCT_ERR_ARG;
+    for (size_t i = 0; i < kv.size(); ++i) // each field at most once
+        for (size_t j = 0; j < i; ++j)
+            if (kv[i].first == kv[j].first)
+                return LCT_ERR_ARG;
     key->kind = kind == "lct" ? LCT_TUNE_LCT : LCT_TUNE_FRFT;
     long long N = 0;
     int E = 0, S = 0, N1 = 0, E1 = 0, E2 = 0, C = 0, RR = 0;
@@ -584,8 +590,40 @@ int parse_entry(const char *line, TuneKey *key, TuneEntry *ent)
     return ent->f.ok ? LCT_OK : LCT_ERR_ARG;
 }
 
+int load_table(const char *path);
+
+// LCT_TUNE_CACHE: a table file read before the first lookup (again whenever
+// the variable names another file).  A missing or invalid file leaves the
+// table as it is; lct_tune_clear does not cause a reload.
+void cache_load()
+{
+    const char *path = getenv("LCT_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    static std::mutex m;
+    static std::string loaded;
+    std::lock_guard<std::mutex> g(m);
+    if (loaded == path)
+        return;
+    loaded = path;
+    (void)load_table(path);
+}
+
+// After an autotune: the whole table to LCT_TUNE_CACHE, through a temporary
+// file renamed over it so that a reader never sees half a table.
+void cache_save()
+{
+    const char *path = getenv("LCT_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    if (lct_tune_save(tmp.c_str()) == LCT_OK && rename(tmp.c_str(), path) != 0)
+        (void)remove(tmp.c_str());
+}
+
 bool lookup(int kind, int64_t N, bool fp64, TuneEntry *e)
 {
+    cache_load();
     std::lock_guard<std::mutex> g(g_mu);
     auto it = g_table.find(TuneKey{kind, N, fp64});
     if (it == g_table.end())
@@ -613,6 +651,19 @@ FsTiling select_fs(int kind, int64_t N, int64_t Nfft, bool fp64)
     if (lookup(kind, N, fp64, &e) && e.two_pass && e.f.ok)
         return e.f;
     return default_fs(Nfft, fp64, kind == LCT_TUNE_FRFT);
+}
+
+void autotune_on_plan(int64_t N, int prec)
+{
+    const char *v = getenv("LCT_AUTOTUNE");
+    if (!v || strcmp(v, "1") != 0 || (prec != LCT_FP32 && prec != LCT_FP64))
+        return;
+    const bool fp64 = prec == LCT_FP64;
+    for (int kind : {LCT_TUNE_LCT, LCT_TUNE_FRFT}) {
+        TuneEntry e;
+        if (!lookup(kind, N, fp64, &e))
+            (void)lct_autotune(N, (lct_precision)prec, kind, 0, nullptr, nullptr); // failure keeps the heuristic
+    }
 }
 
 } // namespace lctk
@@ -661,6 +712,50 @@ template <class F> double time_it(F run, hipStream_t s, int reps)
 }
 
 } // namespace
+
+namespace lctk {
+namespace {
+
+// Reads a table file: every non-comment line must be a valid entry (a line
+// longer than the buffer is invalid), else nothing is taken from the file.
+int load_table(const char *path)
+{
+    if (!path)
+        return LCT_ERR_ARG;
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return LCT_ERR_ARG;
+    std::vector<std::pair<TuneKey, TuneEntry>> got;
+    char line[512];
+    int rc = LCT_OK;
+    while (fgets(line, sizeof line, f)) {
+        const size_t len = strlen(line);
+        if (len == sizeof line - 1 && line[len - 1] != '\n' && !feof(f)) {
+            rc = LCT_ERR_ARG;
+            break;
+        }
+        const char *p = line;
+        while (*p == ' ' || *p == '\t')
+            ++p;
+        if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0)
+            continue;
+        TuneKey k{};
+        TuneEntry e;
+        if ((rc = parse_entry(p, &k, &e)) != LCT_OK)
+            break;
+        got.push_back({k, e});
+    }
+    fclose(f);
+    if (rc != LCT_OK)
+        return rc;
+    std::lock_guard<std::mutex> g(g_mu);
+    for (const auto &kv : got)
+        g_table[kv.first] = kv.second;
+    return LCT_OK;
+}
+
+} // namespace
+} // namespace lctk
 
 extern "C" {
 
@@ -765,36 +860,7 @@ int lct_tune_save(const char *path)
     return (fclose(f) == 0 && ok) ? LCT_OK : LCT_ERR_ARG;
 }
 
-int lct_tune_load(const char *path)
-{
-    if (!path)
-        return LCT_ERR_ARG;
-    FILE *f = fopen(path, "r");
-    if (!f)
-        return LCT_ERR_ARG;
-    std::vector<std::pair<TuneKey, TuneEntry>> got;
-    char line[512];
-    int rc = LCT_OK;
-    while (fgets(line, sizeof line, f)) {
-        const char *p = line;
-        while (*p == ' ' || *p == '\t')
-            ++p;
-        if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0)
-            continue;
-        TuneKey k{};
-        TuneEntry e;
-        if ((rc = parse_entry(p, &k, &e)) != LCT_OK)
-            break;
-        got.push_back({k, e});
-    }
-    fclose(f);
-    if (rc != LCT_OK)
-        return rc; // nothing is taken from a file with an invalid line
-    std::lock_guard<std::mutex> g(g_mu);
-    for (const auto &kv : got)
-        g_table[kv.first] = kv.second;
-    return LCT_OK;
-}
+int lct_tune_load(const char *path) { return load_table(path); }
 
 int lct_autotune(int64_t N, lct_precision prec, int kind, int64_t batch, hipStream_t stream, lct_tune_result *res)
 {
@@ -908,6 +974,7 @@ int lct_autotune(int64_t N, lct_precision prec, int kind, int64_t batch, hipStre
         std::lock_guard<std::mutex> g(g_mu);
         g_table[key] = win;
     }
+    cache_save();
     if (res) {
         res->kind = kind;
         res->candidates = ncand;

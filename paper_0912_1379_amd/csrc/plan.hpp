@@ -54,6 +54,13 @@ FsTiling default_fs(int64_t N, bool fp64, bool frft = false);
 Tiling select_tiling(int kind, int64_t N, int64_t Nfft, bool fp64, size_t extra);
 FsTiling select_fs(int kind, int64_t N, int64_t Nfft, bool fp64);
 
+// With LCT_AUTOTUNE=1 in the environment, times the candidate geometries of
+// both transforms for (N, prec) on the default stream when the table has no
+// entry for them (plan creation calls it; FP32 and FP64 only).  With
+// LCT_TUNE_CACHE=path the table is read from that file before the first
+// lookup and written back after every autotune.
+void autotune_on_plan(int64_t N, int prec);
+
 // Geometry of the split-BF16 matrix-core variant (FP32 data): N a power of
 // two from 256 to 2^24; E = 16, radix-16 stages first.  One pass up to
 // 16384 points, beyond that N = N1 N2 with N1 = 2^floor(log2(N) / 2); a

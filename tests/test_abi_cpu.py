@@ -257,6 +257,7 @@ BAD_LINES = [
     "lct N=1048576 prec=fp32 N1=1024 E1=16 E2=16 C=16 RR=16 rad1=16.16.4 rad2=16.16.2",  # rad2 product
     "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16.1",       # radix 1 not implemented
     "lct N=4096 prec=fp32 E=-16 S=1 rad=16.16.16",        # negative
+    "lct N=4096 prec=fp32 E=16 S=1 rad=16.16.16 S=1",     # a field twice
 ]
 
 
@@ -456,3 +457,119 @@ def test_complex_nodes_helper(lib):
     x = h * (2 * np.arange(N) - N + 1) / 2
     assert np.allclose(y.view(np.complex128), 4 * b * x / np.pi, rtol=1e-15, atol=1e-15)
     assert lib.lct_complex_nodes(N, 0.0, 0.0, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == _lib.LCT_ERR_ARG
+
+
+# --- mutated and random inputs to the host parsers (also run under the sanitized build) ---
+def _mutations(line, g):
+    toks = line.split()
+    out = []
+    for _ in range(60):
+        s = line
+        op = g.integers(0, 8)
+        if op == 0 and s:                                   # drop a character
+            i = g.integers(0, len(s))
+            s = s[:i] + s[i + 1:]
+        elif op == 1:                                       # insert a printable character
+            i = g.integers(0, len(s) + 1)
+            s = s[:i] + chr(int(g.integers(32, 127))) + s[i:]
+        elif op == 2:                                       # a field with a huge or negative value
+            t = list(toks)
+            k = g.integers(1, len(t))
+            key = t[k].split("=")[0]
+            t[k] = key + "=" + g.choice(["99999999999999999999", "-1", "0", "", "2147483648", "1e9", "16.16.16.16.16.16.16.16"])
+            s = " ".join(t)
+        elif op == 3:                                       # duplicate a field
+            t = list(toks)
+            t.insert(int(g.integers(1, len(t) + 1)), t[int(g.integers(1, len(t)))])
+            s = " ".join(t)
+        elif op == 4:                                       # drop a field
+            t = list(toks)
+            del t[int(g.integers(0, len(t)))]
+            s = " ".join(t)
+        elif op == 5:                                       # a very long schedule
+            s = line + "." + ".".join(["2"] * int(g.integers(10, 400)))
+        elif op == 6:                                       # very long line of one token
+            s = "lct " + "N=" + "9" * int(g.integers(50, 5000))
+        else:                                               # shuffled fields
+            t = list(toks[1:])
+            g.shuffle(t)
+            s = toks[0] + " " + " ".join(t)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("N,prec,kind", [(4096, 0, 0), (1 << 20, 1, 0), (2048, 0, 1), (12288, 0, 1)])
+def test_tune_parser_on_mutated_lines(lib, N, prec, kind):
+    """Each mutation of a valid entry is either rejected or accepted as an entry that
+    then reads back unchanged for its own (N, precision, kind)."""
+    g = np.random.default_rng(N + kind)
+    for base in _cands(lib, N, prec, kind)[:4]:
+        for s in _mutations(base, g):
+            lib.lct_tune_clear()
+            rc = lib.lct_tune_set(s.encode())
+            assert rc in (_lib.LCT_OK, _lib.LCT_ERR_ARG), s
+            if rc == _lib.LCT_OK:
+                kv = dict(t.split("=", 1) for t in s.split()[1:])
+                pr = {"fp32": 0, "fp64": 1, "splitbf16": 2}[kv["prec"]]
+                kd = {"lct": 0, "frft": 1}[s.split()[0]]
+                got = _get(lib, int(kv["N"]), pr, kd)
+                assert sorted(got.split()) == sorted(s.split()), (s, got)
+    lib.lct_tune_clear()
+
+
+def test_descriptor_classification_on_random_descriptors(lib):
+    """lct_workspace_size on random descriptor arrays (sizes, kinds, precisions, pads,
+    offsets, parameters drawn wide) returns a status and never reads past nsig entries."""
+    import paper_0912_1379_amd as lct
+    g = np.random.default_rng(11)
+    for _ in range(400):
+        n = int(g.integers(1, 40))
+        d = np.zeros(n, dtype=lct.DESC_DTYPE)
+        d["N"] = g.choice([0, 1, 7, 64, 4096, 65536, 65537, 1 << 24, -5, 2 ** 31 - 1], n)
+        d["kind"] = g.choice([0, 1, 2, -1], n, p=[0.45, 0.45, 0.05, 0.05])
+        d["prec"] = g.choice([0, 1, 2, 9], n, p=[0.7, 0.2, 0.05, 0.05])
+        d["pad"] = g.choice([0, 1], n, p=[0.9, 0.1])
+        d["offset"] = g.integers(-10, 1 << 40, n)
+        d["p"] = g.normal(0, 1, (n, 4)) * g.choice([1, 1e300], (n, 4), p=[0.9, 0.1])
+        sz = ctypes.c_size_t(0)
+        rc = lib.lct_workspace_size(d.ctypes.data, n, ctypes.byref(sz))  # an array of exactly n entries
+        assert rc in (_lib.LCT_OK, _lib.LCT_ERR_ARG, _lib.LCT_ERR_UNSUPPORTED, _lib.LCT_ERR_UNSUPPORTED_N,
+                      _lib.LCT_ERR_NOT_UNIMODULAR, _lib.LCT_ERR_DOMAIN), rc
+
+
+def test_tune_cache_environment(lib, tmp_path, monkeypatch):
+    """LCT_TUNE_CACHE: the table is read from the named file before a lookup (again when
+    the variable names another file); a missing or invalid file leaves the heuristic."""
+    lib.lct_tune_clear()
+    pick = _cands(lib, 4096, 0, 0)[2]
+    good = tmp_path / "good.txt"
+    good.write_text("# cache\n" + pick + "\n")
+    bad = tmp_path / "bad.txt"
+    bad.write_text(pick.replace("lct N=4096", "lct N=8192") + "\n" + "x" * 600 + "\n")
+    heur = _get(lib, 4096, 0, 0)
+    assert heur != pick
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(tmp_path / "missing.txt"))
+    assert _get(lib, 4096, 0, 0) == heur
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(bad))   # an over-long line: nothing taken
+    assert _get(lib, 4096, 0, 0) == heur
+    assert _get(lib, 8192, 0, 0) == _cands(lib, 8192, 0, 0)[0]
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(good))
+    assert _get(lib, 4096, 0, 0) == pick
+    lib.lct_tune_clear()                               # clearing does not reload the same file
+    assert _get(lib, 4096, 0, 0) == heur
+    monkeypatch.delenv("LCT_TUNE_CACHE")
+    assert lib.lct_tune_load(str(bad).encode()) == _lib.LCT_ERR_ARG
+
+
+def test_autotune_flag_without_a_device_keeps_the_heuristic(lib, monkeypatch):
+    """LCT_AUTOTUNE=1 on a host without a usable device: plan creation still succeeds
+    (the failed tuning leaves the heuristic)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+    lib.lct_tune_clear()
+    monkeypatch.setenv("LCT_AUTOTUNE", "1")
+    rc, h = plan(lib, N=512)
+    assert rc == _lib.LCT_OK
+    lib.lct_plan_destroy(h)
+    assert _get(lib, 512, 0, 0) == _cands(lib, 512, 0, 0)[0]

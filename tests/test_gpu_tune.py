@@ -100,3 +100,39 @@ def test_autotune_records_a_candidate_and_keeps_parity(N, kind, dtype):
     case = _lct_case(N, dtype) if kind == "lct" else _frft_case(N, dtype)
     errs = (_errors_lct if kind == "lct" else _errors_frft)(*case)
     assert max(errs) <= TOL[dtype], errs
+
+
+def test_autotune_env_flags_tune_at_plan_creation_and_write_the_cache(tmp_path, monkeypatch):
+    """LCT_AUTOTUNE=1: plan creation tunes both transforms of its length and
+    precision; LCT_TUNE_CACHE: the table is written there and a cleared table
+    reads it back; the tuned plan still matches the oracle."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LCT_AUTOTUNE", "1")
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(cache))
+    N = 2048
+    plan = lct.lct_plan_create(N, 0.5, 1.0, -0.5, 1.0)
+    try:
+        text = cache.read_text()
+        lines = [ln for ln in text.splitlines() if ln and not ln.startswith("#")]
+        assert any(ln.startswith(f"lct N={N} prec=fp32 ") for ln in lines), text
+        assert any(ln.startswith(f"frft N={N} prec=fp32 ") for ln in lines), text
+        tuned = lct.lct_tune_get(N, lct.LCT_FP32, "lct")
+        assert tuned in lines
+        x = dev(workloads.chirped_gaussians(oracle.nodes(N), workloads.gaussian_params(1, np.random.default_rng(4))),
+                torch.complex64)
+        y = lct.lct_exec(plan, x).cpu().numpy().astype(np.complex128)
+        ref = oracle.lct(x.cpu().numpy().astype(np.complex128)[0], 0.5, 1.0, -0.5, 1.0)
+        assert rel_rows(y[0], ref)[0] <= TOL[torch.complex64]
+    finally:
+        lct.lct_plan_destroy(plan)
+    # a second plan of the same length finds the entries and does not tune again
+    mtime = cache.stat().st_mtime_ns
+    lct.lct_plan_destroy(lct.lct_plan_create(N, 0.0, 1.0, -1.0, 0.0))
+    assert cache.stat().st_mtime_ns == mtime
+    monkeypatch.delenv("LCT_AUTOTUNE")
+    lct.lct_tune_clear()
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(tmp_path / "other.txt"))  # missing file: heuristics
+    heur = lct.lct_tune_get(N, lct.LCT_FP32, "lct")
+    monkeypatch.setenv("LCT_TUNE_CACHE", str(cache))
+    assert lct.lct_tune_get(N, lct.LCT_FP32, "lct") == tuned
+    assert heur == lct.lct_tune_candidates(N, lct.LCT_FP32, "lct")[0]
