@@ -362,27 +362,76 @@ __device__ __forceinline__ int umod24(int a, int m)
 __device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
 __host__ __device__ constexpr int lds_elems(int N) { return N + (N >> 4) + 1; }
 
+// a W16^k, W16 = e^{-2 pi i / 16}, for a compile-time k: the multiples of 4
+// are free, the rest one product by a constant.
+template <int k, typename R> __device__ __forceinline__ C<R> mul_w16(C<R> a)
+{
+    constexpr int m = k & 15;
+    if constexpr (m >= 8) {
+        const C<R> b = mul_w16<m - 8>(a);
+        return C<R>{-b.x, -b.y};
+    } else if constexpr (m >= 4) {
+        return cmul_mi(mul_w16<m - 4>(a));
+    } else if constexpr (m == 0) {
+        return a;
+    } else if constexpr (m == 1) {
+        return cmul(a, C<R>{K<R>::C8, -K<R>::S8});
+    } else if constexpr (m == 2) {
+        return cmul(a, C<R>{K<R>::SQH, -K<R>::SQH});
+    } else {
+        return cmul(a, C<R>{K<R>::S8, -K<R>::C8});
+    }
+}
+
+template <int E, int RAD, int I, int R0, typename R>
+__device__ __forceinline__ void twiddles_shifted(const C<R> *w0, C<R> *w)
+{
+    if constexpr (R0 < RAD) {
+        w[R0] = mul_w16<(I * R0 * (16 / E)) & 15>(w0[R0]);
+        twiddles_shifted<E, RAD, I, R0 + 1>(w0, w);
+    }
+}
+
+// Butterfly i's twiddles from butterfly 0's when T Q = Ns: positions b = t + T i
+// do not wrap modulo Ns, so j_i = j_0 + T i and the base angle moves by
+// -T i / (Ns RAD) = -i / E turns: w_i^r = w_0^r W_E^(i r).  E = 8 or 16.
+template <int E, int RAD, int I, typename R> __device__ __forceinline__ void twiddles_next(const C<R> *w0, C<R> *w)
+{
+    twiddles_shifted<E, RAD, I, 1>(w0, w);
+}
+
 // One Stockham stage of radix RAD on the E register values of thread t.
 // Input slot i + Q r (Q = E / RAD) holds position t + T (i + Q r); butterfly
 // i has index b = t + T i and twiddle W_{Ns RAD}^{(b mod Ns) r}.  Outputs are
 // left in place: slot i + Q s holds output s of butterfly i.
-template <int E, int RAD, typename R>
-__device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
+template <int E, int RAD, int I, typename R>
+__device__ __forceinline__ void stage_compute_from(C<R> *v, int t, int T, int Ns, C<R> *w0)
 {
     constexpr int Q = E / RAD;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    if constexpr (I < Q) {
         C<R> u[RAD];
 #pragma unroll
         for (int r = 0; r < RAD; ++r)
-            u[r] = v[i + Q * r];
+            u[r] = v[I + Q * r];
         if (Ns > 1) {
-            int b = t + T * i;
-            int j = umod24(b, Ns);
-            // base angle -j / (Ns RAD) turns (exact for power-of-two Ns RAD)
-            const R inv = (R)1 / (R)(Ns * RAD);
             C<R> w[RAD];
-            twiddles<RAD>((R)(-j) * inv, w);
+            if constexpr (I > 0 && (E == 8 || E == 16)) {
+                if (T * Q == Ns) {
+                    twiddles_next<E, RAD, I>(w0, w);
+                } else {
+                    const int j = umod24(t + T * I, Ns);
+                    twiddles<RAD>((R)(-j) * ((R)1 / (R)(Ns * RAD)), w);
+                }
+            } else {
+                // base angle -j / (Ns RAD) turns (exact for power-of-two Ns RAD)
+                const int j = umod24(t + T * I, Ns);
+                twiddles<RAD>((R)(-j) * ((R)1 / (R)(Ns * RAD)), w);
+                if constexpr (I == 0) {
+#pragma unroll
+                    for (int r = 1; r < RAD; ++r)
+                        w0[r] = w[r];
+                }
+            }
 #pragma unroll
             for (int r = 1; r < RAD; ++r)
                 u[r] = cmul(u[r], w[r]);
@@ -390,8 +439,16 @@ __device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
         dft<RAD>(u);
 #pragma unroll
         for (int s = 0; s < RAD; ++s)
-            v[i + Q * s] = u[s];
+            v[I + Q * s] = u[s];
+        stage_compute_from<E, RAD, I + 1>(v, t, T, Ns, w0);
     }
+}
+
+template <int E, int RAD, typename R>
+__device__ __forceinline__ void stage_compute(C<R> *v, int t, int T, int Ns)
+{
+    C<R> w0[RAD];
+    stage_compute_from<E, RAD, 0>(v, t, T, Ns, w0);
 }
 
 // What one LDS exchange moves: PART < 0 whole complex values (a C<R> array),

@@ -398,10 +398,16 @@ __device__ __forceinline__ double gauss_logmod(const GaussPoly &g, int e)
     const double m = (double)(g.m0 + g.D * e);
     return g.mag * (m * m);
 }
-// FP32: the value at any e (no state beyond the coefficients).
+// FP32: the value at any e (no state beyond the coefficients).  The modulus
+// is 2^x by the hardware base-2 exponential, x = log2(e) mag m^2 formed in
+// FP64 and rounded to FP32 once (the exponent's rounding is then that of the
+// natural-log exponent rounded for expf; the library expf costs about ten
+// more instructions per value).  x below the FP32 range gives 0.
 __device__ __forceinline__ C<float> gauss_at(const GaussPoly &g, int e)
 {
-    return cscale(chirp_at<float>(g.ph, e), expf((float)fmax(gauss_logmod(g, e), -200.0)));
+    const double m = (double)(g.m0 + g.D * e);
+    const float x = (float)((g.mag * 1.4426950408889634074) * (m * m));
+    return cscale(chirp_at<float>(g.ph, e), __builtin_amdgcn_exp2f(x));
 }
 template <typename R> struct GaussSeq;
 template <> struct GaussSeq<float> {
