@@ -24,9 +24,11 @@ namespace lctk {
 // every store writes consecutive k1 of one transposed row.
 // NFIX > 0: the column length N1 = NFIX with its compile-time radix schedule
 // (constant strides and radices keep the register demand low enough for the
-// 1024-thread launch bound without spills).
+// 1024-thread launch bound without spills).  The 256-thread matrix-core
+// instantiations ask for three waves per SIMD: 162-166 VGPRs, no spills, three
+// work-groups per CU instead of two (unbounded they take about 200).
 template <typename R, int E, int MODE, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
-__global__ __launch_bounds__(LB) void k_fs1(
+__global__ __launch_bounds__(LB, (MF && LB == 256) ? 3 : 1) void k_fs1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FsArgs args)
 {
     using V = typename Vec<R>::T;
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(LB) void k_fs1(
 // fastest, so loads and stores both touch RR consecutive samples per row.
 // NFIX > 0: the row length N2 = NFIX with its compile-time radix schedule.
 template <typename R, int E, int MODE, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
-__global__ __launch_bounds__(LB) void k_fs2(typename Vec<R>::T *__restrict__ out,
+__global__ __launch_bounds__(LB, (MF && LB == 256) ? 3 : 1) void k_fs2(typename Vec<R>::T *__restrict__ out,
                                                                        FsArgs args)
 {
     using V = typename Vec<R>::T;

@@ -95,7 +95,10 @@ __device__ __forceinline__ void lane_chirp4(const LaneChirp &L, int q, C<float> 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_lct_mf4096(const float2 *__restrict__ in, float2 *__restrict__ out,
+// Four waves per SIMD asked of the register allocation: it then fits in 101
+// VGPRs without spills (134 VGPRs and 34 AGPRs unbounded, three work-groups per
+// CU), and four 34.8 KiB work-groups share a CU's LDS.
+__global__ __launch_bounds__(256, 4) void k_lct_mf4096(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                      LctArgs args)
 {
     constexpr int N = 4096, N16 = 256;
