@@ -486,6 +486,102 @@ def frft_errors(out, x, y, ysh, z, N):
         out["shared_order"]["rel_l2_max"] = max(esh)
 
 
+def bench_next(args):
+    """The widened entry points on 4096 signals x N = 4096 chirped Gaussians, FP32 steps with FP64
+    legs: the same-grid LCT of a damped complex matrix (lct_same_grid_exec, one length-2N
+    convolution per signal with the kernel's spectrum computed once), the LCT at the Algorithm's
+    complex output nodes (lct_complex_exec) for the bilateral Laplace matrix (0, i, 0), and the
+    aliasing-aware LCT (lct_exec_oversampled: interpolation onto the P times finer grid, the
+    transform there, the middle block; P = 4 in FP32, 2 in FP64).  The step is the complex-node LCT; each leg
+    reports its time, rate, the relative L2 error of 2 signals against the oracle and the oracle's
+    time on them."""
+    import torch
+    import workloads
+    import paper_0912_1379_amd as lct
+    import oracle
+
+    B, N = args.signals, args.N
+    g = workloads.rng(6)
+    gp = workloads.gaussian_params(B, g)
+    xn, _ = lct.lct_nodes(N, 1.0)
+    f = workloads.chirped_gaussians(xn, gp)
+    samples = B * N
+    legs = {}
+    cpu = {"seconds": 0.0, "samples": 0}
+
+    def leg(name, dt, run, ref_fn, nref=2):
+        x = torch.from_numpy(f).to("cuda").to(dt)
+        y = torch.empty_like(x)
+        steps = args.steps if dt == torch.complex64 else max(3, args.steps // 2)
+        ms, ms_kernel, wall = time_launches(lambda: run(x, y), steps, args.warmup)
+        out = {"ms_per_step": ms, "kernel_ms": ms_kernel, "value": samples / (ms * 1e-3),
+               "achieved_GBps": (16.0 if dt == torch.complex64 else 32.0) * samples / (ms_kernel * 1e-3) / 1e9}
+        if not args.no_cpu_baseline:
+            errs = []
+            t0 = time.perf_counter()
+            for s in range(nref):
+                fin = x[s].cpu().numpy().astype(np.complex128)
+                ref = ref_fn(fin)
+                errs.append(float(np.linalg.norm(y[s].cpu().numpy() - ref) / np.linalg.norm(ref)))
+            el = time.perf_counter() - t0
+            cpu["seconds"] += el
+            cpu["samples"] += nref * N
+            out["rel_l2"] = {"max": max(errs), "signals": nref}
+        print(f"[bench] {name}: {ms * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+        legs[name] = out
+        return out
+
+    # complex output nodes, bilateral Laplace (0, i, 0)
+    for name, dt in (("complex_nodes_f32", torch.complex64), ("complex_nodes_f64", torch.complex128)):
+        if dt == torch.complex128 and args.no_fp64:
+            continue
+        leg(name, dt, lambda x, y: lct.lct_complex_exec(x, 0.0, 1j, 0.0, out=y),
+            lambda fin: oracle.lct_complex(fin, 0.0, 1j, 0.0))
+    # same grid, a damped matrix (Toeplitz form)
+    a, b, d = 0.9 + 0.1j, 0.6 - 0.2j, 1.1 + 0.05j
+    for name, dt in (("same_grid_f32", torch.complex64), ("same_grid_f64", torch.complex128)):
+        if dt == torch.complex128 and args.no_fp64:
+            continue
+        prec = lct.LCT_FP64 if dt == torch.complex128 else lct.LCT_FP32
+        ws = torch.empty(lct.frft_workspace_size(N, prec, B), dtype=torch.uint8, device="cuda")
+        leg(name, dt, lambda x, y: lct.lct_same_grid_exec(x, a, b, d, out=y, ws=ws),
+            lambda fin: oracle.lct_same_grid(fin, a, b, d))
+    # aliasing-aware mode on a matrix whose pre-chirp aliases on the plain grid (a/b = 16): P = 4 in
+    # FP32 (16384-point fine grid), P = 2 in FP64 (8192, the longest FP64 single pass)
+    M = (8.0, 0.5, (8.0 * 0.3 - 1.0) / 0.5, 0.3)
+    for name, dt, p in (("oversampled_f32", torch.complex64, 4), ("oversampled_f64", torch.complex128, 2)):
+        if dt == torch.complex128 and args.no_fp64:
+            continue
+        prec = lct.LCT_FP64 if dt == torch.complex128 else lct.LCT_FP32
+        plan = lct.lct_plan_create(N, *M, precision=prec)
+        ws = torch.empty(lct.lct_oversampled_workspace_size(N, p, prec, B), dtype=torch.uint8, device="cuda")
+        leg(name, dt, lambda x, y: lct.lct_exec_oversampled(plan, p, x, out=y, ws=ws),
+            lambda fin: oracle.lct_oversampled(fin, *M, p))
+        legs[name]["P"] = p
+    head = legs["complex_nodes_f32"]
+    out = {
+        "metric": "complex samples/s, LCT of a complex matrix at the Algorithm's complex output nodes",
+        "value": head["value"], "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"complex-matrix, same-grid and oversampled LCTs, {B} signals x N={N}",
+                   "signals": B, "N": N, "complex_matrix": "(0, i, 0): bilateral Laplace",
+                   "same_grid_matrix": [str(a), str(b), str(d)],
+                   "oversampled": {"M": list(M), "P": {"f32": 4, "f64": 2}}},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": head["achieved_GBps"] / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_lct_cx (FP32)",
+                     "kernel_ms": head["kernel_ms"], "algorithmic_bytes_per_launch": 16.0 * samples},
+        "legs": legs,
+    }
+    if not args.no_cpu_baseline:
+        out["rel_l2"] = head["rel_l2"]
+        out["cpu_baseline"] = {"value": cpu["samples"] / cpu["seconds"], "unit": "complex samples/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"2 whole signals per leg (dense N={N} sums; the oversampled legs on the "
+                                         f"finer grid), {cpu['seconds']:.1f} s in all"}
+    return out
+
+
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "f64": 78.6}
 
 
@@ -653,10 +749,12 @@ def main():
                     help="frft workload: skip the shared-order (precomputed kernel spectrum) leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
-    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft", "xft"], default="batched",
+    ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft", "xft", "next"],
+                    default="batched",
                     help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
                          "large: 16 x 2^20; fit: autograd step at 256 x 2048; frft: 4096 x N=4096 fractional; "
-                         "xft: 4096 x N=4096 exact-node transform on the matrix cores")
+                         "xft: 4096 x N=4096 exact-node transform on the matrix cores; next: complex-matrix, "
+                         "same-grid and oversampled LCTs at 4096 x N=4096")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -667,7 +765,7 @@ def main():
 
     if args.workload != "batched":
         fn = {"ragged": bench_ragged, "large": bench_large, "fit": bench_fit, "frft": bench_frft,
-              "xft": bench_xft}[args.workload]
+              "xft": bench_xft, "next": bench_next}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

@@ -14,42 +14,50 @@
 namespace lctk {
 
 // The diagonal exp(w n^2) (n = 2p - N + 1) times the index phase
-// (N - 1) p / (2N) at this thread's positions p = t + T e.
+// (N - 1) p / (2N) at this thread's positions p = t + T e, e = 0, 1, ...
+__device__ __forceinline__ GaussPoly cx_poly(double mag, double hi, double lo, int t, int T, int N, double inv2N)
+{
+    GaussPoly g = gauss_poly(mag, hi, lo, 2 * t - N + 1, 2 * T);
+    g.ph.A = frac_turns(g.ph.A + index_turns(t, N, inv2N));
+    g.ph.B = frac_turns(g.ph.B + index_turns(T, N, inv2N));
+    return g;
+}
+
 template <typename R> struct CxDiag;
 template <> struct CxDiag<float> {
     GaussPoly g;
     __device__ CxDiag(double mag, double hi, double lo, int t, int T, int N, double inv2N)
-        : g(gauss_poly(mag, hi, lo, 2 * t - N + 1, 2 * T))
+        : g(cx_poly(mag, hi, lo, t, T, N, inv2N))
     {
-        g.ph.A = frac_turns(g.ph.A + index_turns(t, N, inv2N));
-        g.ph.B = frac_turns(g.ph.B + index_turns(T, N, inv2N));
     }
-    __device__ __forceinline__ C<float> at(int e) const { return gauss_at(g, e); }
+    __device__ __forceinline__ C<float> at(int e) { return gauss_at(g, e); }
 };
 template <> struct CxDiag<double> {
+    // values in order e = 0, 1, ... (at(e) once per e): the phase walked by
+    // products as ChirpSeq<double> (the library sine/cosine costs tens of FP64
+    // operations per call), the modulus exp(mag m^2) from the exact m^2
     GaussPoly g;
+    ChirpSeq<double> c;
     __device__ CxDiag(double mag, double hi, double lo, int t, int T, int N, double inv2N)
-        : g(gauss_poly(mag, hi, lo, 2 * t - N + 1, 2 * T))
+        : g(cx_poly(mag, hi, lo, t, T, N, inv2N)), c(g.ph)
     {
-        g.ph.A = frac_turns(g.ph.A + index_turns(t, N, inv2N));
-        g.ph.B = frac_turns(g.ph.B + index_turns(T, N, inv2N));
     }
-    __device__ __forceinline__ C<double> at(int e) const
-    {
-        const double fe = (double)e;
-        const double u = fma(g.ph.B, fe, fma(g.ph.C, fe * fe, g.ph.A));
-        return cscale(cis_turns(frac_turns(u)), exp(fmax(gauss_logmod(g, e), -1000.0)));
-    }
+    __device__ __forceinline__ C<double> at(int e) { return cscale(c.next(), exp(fmax(gauss_logmod(g, e), -1000.0))); }
 };
 
-template <typename R, int E>
-__global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_cx(
-    const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, CxArgs a)
+// NFIX > 0: the length's compile-time radix schedule (E = 16); with
+// NFIX / E >= 256 threads one signal per work-group.  HX: LDS exchanged in
+// real and imaginary halves (lds_elems(N) R per signal).
+template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool HX = false>
+__global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct_cx(const typename Vec<R>::T *__restrict__ in,
+                                                           typename Vec<R>::T *__restrict__ out, CxArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<R> *smem = reinterpret_cast<C<R> *>(smem_raw);
-    const int N = a.N, T = a.T;
-    const int sl = (int)threadIdx.x / T;
+    const int N = NFIX > 0 ? NFIX : a.N;
+    const int T = NFIX > 0 ? NFIX / E : a.T;
+    constexpr bool ONE = NFIX > 0 && NFIX / E >= 256;
+    const int sl = ONE ? 0 : (int)threadIdx.x / T;
     const int t = (int)threadIdx.x - sl * T;
     const int64_t sig = (int64_t)blockIdx.x * a.S + sl;
     const bool live = sig < a.batch;
@@ -61,14 +69,19 @@ __global__ __launch_bounds__(max_block(sizeof(R) == 8, E)) void k_lct_cx(
     for (int e = 0; e < E; ++e)
         v[e] = live ? ldc<R>(src + t + T * e) : C<R>{(R)0, (R)0};
     {
-        const CxDiag<R> pre(a.k.pre_mag, a.k.pre_hi, a.k.pre_lo, t, T, N, inv2N);
+        CxDiag<R> pre(a.k.pre_mag, a.k.pre_hi, a.k.pre_lo, t, T, N, inv2N);
 #pragma unroll
         for (int e = 0; e < E; ++e)
             v[e] = cmul(v[e], pre.at(e));
     }
-    fft_lds<E>(v, smem + (size_t)sl * lds_elems(N), t, T, a.sc);
+    if constexpr (NFIX > 0 && HX)
+        fft_lds_fixed_half<E, NFIX>(v, reinterpret_cast<R *>(smem_raw) + (size_t)sl * lds_elems(N), t);
+    else if constexpr (NFIX > 0)
+        fft_lds_fixed<E, NFIX>(v, smem + (size_t)sl * lds_elems(N), t);
+    else
+        fft_lds<E>(v, smem + (size_t)sl * lds_elems(N), t, T, a.sc);
     if (live) {
-        const CxDiag<R> post(a.k.post_mag, a.k.post_hi, a.k.post_lo, t, T, N, inv2N);
+        CxDiag<R> post(a.k.post_mag, a.k.post_hi, a.k.post_lo, t, T, N, inv2N);
         const C<R> amp{(R)a.k.amp_re, (R)a.k.amp_im};
 #pragma unroll
         for (int e = 0; e < E; ++e)

@@ -21,6 +21,19 @@ hipError_t dispatch_frft_f64(int E, const void *in, void *out, const FrArgs &a, 
             break;
         }
     }
+    // E = 8, the FP64 default (16 values of a row and of the kernel per thread
+    // would not fit the registers of a 512-thread work-group)
+    if (E == 8 && is_fixed_sched(a.sc, 2 * a.N, 8)) {
+        switch (2 * a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_frft_t<double, 8, n>(in, out, a, nb, bs, lds, s);
+            X(2048) X(4096) X(8192)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

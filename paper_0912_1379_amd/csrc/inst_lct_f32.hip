@@ -32,4 +32,22 @@ hipError_t dispatch_lct_f32(int E, const void *in, void *out, const LctArgs &a, 
     }
 }
 
+// The windowed forward transform (the aliasing-aware mode's fine grid): fixed
+// lengths with one signal per work-group.
+hipError_t dispatch_lct_window_f32(int E, const void *in, void *out, const LctArgs &a, int nb, int bs, size_t lds,
+                                   hipStream_t s)
+{
+    if (E != 16 || !is_fixed_sched(a.sc, a.N, 16) || a.S != 1 || a.mode != MODE_FWD)
+        return hipErrorNotSupported;
+    switch (a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_lct_window_t<float, 16, n>(in, out, a, nb, bs, lds, s);
+        X(4096) X(8192) X(16384)
+#undef X
+    default:
+        return hipErrorNotSupported;
+    }
+}
+
 } // namespace lctk

@@ -127,8 +127,10 @@ template <> struct ChirpSeq<double> {
 // products; see mfma_fft.hpp).  HX (fixed lengths): LDS exchanges in real and
 // imaginary halves, lds_elems(N) R of LDS per signal, and at least three waves
 // per SIMD asked of the register allocation.
+// WIN (forward, fixed lengths): only the outputs at positions
+// [win_off, win_off + win_n) are stored, as win_n contiguous values per signal.
 template <typename R, int E, int NFIX, int MODE, bool MF = false, int LB = max_block(sizeof(R) == 8, E),
-          bool HX = false>
+          bool HX = false, bool WIN = false>
 __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, LctArgs args)
 {
@@ -224,7 +226,13 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct(
                 y = cscale(cmul(v[e], cout.next()), mag);
             else
                 y = cconj(cmul(v[e], cout.next()));
-            Buf<R>::store(y, rout, voff, e * sstep);
+            if constexpr (WIN) {
+                const unsigned q = (unsigned)(t + T * e - args.win_off);
+                if (q < (unsigned)args.win_n)
+                    stc<R>(out + sig * args.win_n + q, y);
+            } else {
+                Buf<R>::store(y, rout, voff, e * sstep);
+            }
         }
     }
 }
@@ -586,6 +594,19 @@ inline hipError_t launch_lct_t(const void *in, void *out, const LctArgs &a, int 
     return hipGetLastError();
 }
 
+// The forward transform storing only the window [a.win_off, a.win_off + a.win_n).
+template <typename R, int E, int NFIX, int LB = max_block(sizeof(R) == 8, E)>
+inline hipError_t launch_lct_window_t(const void *in, void *out, const LctArgs &a, int nblocks, int block, size_t lds,
+                                      hipStream_t s)
+{
+    auto kern = k_lct<R, E, NFIX, MODE_FWD, false, LB, false, true>;
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(block), lds, s, (const typename Vec<R>::T *)in,
+                       (typename Vec<R>::T *)out, a);
+    return hipGetLastError();
+}
+
 template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_pgrad_t(const void *f, const void *g, double *grad4, const LctArgs &a, int nblocks,
                                  int block, size_t lds, hipStream_t s)
@@ -603,6 +624,10 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
                                 hipStream_t s)
 {
     auto kern = k_frft<R, E, LFIX, LB>;
+    if constexpr (LFIX > 0 && sizeof(R) == 8 && E == 8) {
+        if (a.spec_mode == SPEC_READ)
+            kern = k_frft<R, E, LFIX, LB, true>;
+    }
     if constexpr (LFIX > 0 && sizeof(R) == 4) {
         if (a.spec_mode == SPEC_READ) {
             kern = k_frft<R, E, LFIX, LB, true>;

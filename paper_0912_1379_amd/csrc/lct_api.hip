@@ -287,6 +287,33 @@ int lct_launch(const Tiling &tl, int64_t N, bool fp64, const double *M4, const L
     return hip_status(launch_lct(fp64, tl.E, in, out, a, (int)nb, tl.block, tl.lds, s));
 }
 
+// Single-pass forward transform of length N storing only the outputs
+// [off, off + n) of each signal, n per signal at out; LCT_ERR_UNSUPPORTED
+// where the geometry has no windowed instantiation (the caller then
+// transforms in full and copies the window).
+int lct_launch_window(int64_t N, bool fp64, const LctConst *k, const void *in, void *out, int64_t batch, int off,
+                      int n, hipStream_t s)
+{
+    const Tiling tl = select_tiling(LCT_TUNE_LCT, N, N, fp64, 0);
+    if (!tl.ok || tl.mf || tl.S != 1)
+        return LCT_ERR_UNSUPPORTED;
+    LctArgs a{};
+    a.N = (int)N;
+    a.T = tl.T;
+    a.S = tl.S;
+    a.mode = 0;
+    a.batch = batch;
+    a.k = *k;
+    a.nc = n_const_host(N);
+    a.sc = tl.sc;
+    a.win_off = off;
+    a.win_n = n;
+    if (batch > INT32_MAX)
+        return LCT_ERR_ARG;
+    const hipError_t e = launch_lct_window(fp64, tl.E, in, out, a, (int)batch, tl.block, tl.lds, s);
+    return e == hipErrorNotSupported ? LCT_ERR_UNSUPPORTED : hip_status(e);
+}
+
 int fs_launch(const FsTiling &f, int64_t N, bool fp64, const double *M4, const LctConst *k, int mode, const void *in,
               void *out, int64_t batch, hipStream_t s)
 {
@@ -659,8 +686,13 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
     // values per thread: E divides N (and so P N), schedules with radices
     // dividing E exist for both lengths, at most 1024 threads
     InterpArgs a{};
+    // (FP64 tries 8 first: at E = 16 the interpolation kernel spills)
     int E = 0;
-    for (int cand : {16, 20, 24, 12, 10, 8, 15, 6, 5, 4, 3, 2}) {
+    static const int widths32[] = {16, 20, 24, 12, 10, 8, 15, 6, 5, 4, 3, 2};
+    static const int widths64[] = {8, 16, 12, 10, 20, 24, 6, 15, 5, 4, 3, 2};
+    const int *widths = fp64 ? widths64 : widths32;
+    for (int w = 0; w < 12; ++w) {
+        const int cand = widths[w];
         if (N % cand || M / cand > 1024 || !interp_width_ok(cand))
             continue;
         const Sched s1 = greedy_sched(N, cand, 16, false), s2 = greedy_sched(M, cand, 16, false);
@@ -689,9 +721,15 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
     const LctConst k = lct_const_scaled(M, p->a, p->b, p->c, p->d, 1.0 / sqrt((double)P));
     if (!lct_const_finite(k))
         return LCT_ERR_ARG;
+    // the fine transform stores only its middle block straight to out where a
+    // windowed instantiation exists; otherwise in full, then the window is copied
+    const int off = (int)((P - 1) * N / 2);
+    rc = lct_launch_window(M, fp64, &k, ws, out, batch, off, (int)N, stream);
+    if (rc != LCT_ERR_UNSUPPORTED)
+        return rc;
     if ((rc = lct_run(M, fp64, false, nullptr, &k, 0, ws, ws, batch, stream)))
         return rc;
-    return hip_status(launch_window(fp64, ws, out, (int)N, (int)M, (int)((P - 1) * N / 2), batch, stream));
+    return hip_status(launch_window(fp64, ws, out, (int)N, (int)M, off, batch, stream));
 }
 
 int lct_complex_exec(int64_t N, lct_precision prec, double a_re, double a_im, double b_re, double b_im, double d_re,

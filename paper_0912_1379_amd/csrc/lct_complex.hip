@@ -5,18 +5,46 @@
 namespace lctk {
 
 namespace {
+template <typename R, int E, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool HX = false>
+hipError_t launch_one(const void *in, void *out, const CxArgs &a, int nb, int bs, size_t lds, hipStream_t s)
+{
+    using V = typename Vec<R>::T;
+    auto kern = k_lct_cx<R, E, NFIX, LB, HX>;
+    if (hipError_t r = allow_lds((const void *)kern, lds); r != hipSuccess)
+        return r;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, (const V *)in, (V *)out, a);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_cx_t(int E, const void *in, void *out, const CxArgs &a, int nb, int bs, size_t lds, hipStream_t s)
 {
-    using V = typename Vec<R>::T;
+    // compile-time schedules for the common lengths (as the real-matrix LCT);
+    // the instantiations with N / 16 >= 256 threads take one signal per work-group
+    if (E == 16 && is_fixed_sched(a.sc, a.N, 16) && (a.N / 16 < 256 || a.S == 1)) {
+        if constexpr (sizeof(R) == 8) {
+            if (a.N == 4096 && bs == 256)
+                return launch_one<double, 16, 4096, 256, true>(in, out, a, nb, bs,
+                                                               (size_t)lds_elems(4096) * sizeof(double), s);
+        }
+        switch (a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_one<R, 16, n>(in, out, a, nb, bs, lds, s);
+            X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#undef X
+        case 16384:
+            if constexpr (sizeof(R) == 4)
+                return launch_one<R, 16, 16384>(in, out, a, nb, bs, lds, s);
+            break;
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
-    case e: {                                                                                                        \
-        if (hipError_t r = allow_lds((const void *)k_lct_cx<R, e>, lds); r != hipSuccess)                             \
-            return r;                                                                                                \
-        hipLaunchKernelGGL((k_lct_cx<R, e>), dim3(nb), dim3(bs), lds, s, (const V *)in, (V *)out, a);                 \
-        return hipGetLastError();                                                                                    \
-    }
+    case e:                                                                                                          \
+        return launch_one<R, e>(in, out, a, nb, bs, lds, s);
         LCT_E_LIST(X)
 #undef X
     default:

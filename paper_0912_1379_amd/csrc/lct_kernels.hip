@@ -34,6 +34,13 @@ hipError_t launch_lct(bool fp64, int E, const void *in, void *out, const LctArgs
     return fp64 ? dispatch_lct_f64(E, in, out, a, nb, bs, lds, s) : dispatch_lct_f32(E, in, out, a, nb, bs, lds, s);
 }
 
+hipError_t launch_lct_window(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nb, int bs,
+                             size_t lds, hipStream_t s)
+{
+    return fp64 ? dispatch_lct_window_f64(E, in, out, a, nb, bs, lds, s)
+                : dispatch_lct_window_f32(E, in, out, a, nb, bs, lds, s);
+}
+
 hipError_t launch_pgrad(bool fp64, int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,
                         int bs, size_t lds, hipStream_t s)
 {

@@ -26,6 +26,8 @@ struct LctArgs {
     LctConst k;     // constants when M4 is null
     NConst nc;      // N-only constants (per-signal constants derive from them)
     Sched sc;       // radix schedule of the length-N DFT
+    int win_off;    // windowed instantiations: output positions [win_off, win_off + win_n)
+    int win_n;      //   of each signal, stored contiguously (win_n per signal)
 };
 
 // Kernel-spectrum modes of the single-pass fractional transform.
@@ -71,6 +73,11 @@ __host__ __device__ constexpr int max_block(bool fp64, int E)
 
 hipError_t launch_lct(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nblocks, int block,
                       size_t lds, hipStream_t s);
+// Forward transform storing only a.win_n outputs from position a.win_off per
+// signal (fixed lengths with one signal per work-group); hipErrorNotSupported
+// where no such instantiation exists.
+hipError_t launch_lct_window(bool fp64, int E, const void *in, void *out, const LctArgs &a, int nblocks, int block,
+                             size_t lds, hipStream_t s);
 hipError_t launch_pgrad(bool fp64, int E, const void *f, const void *g, double *grad4, const LctArgs &a,
                         int nblocks, int block, size_t lds, hipStream_t s);
 hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs &a, int nblocks, int block,
@@ -82,7 +89,9 @@ hipError_t launch_frft(bool fp64, int E, const void *in, void *out, const FrArgs
     hipError_t dispatch_frft_##tag(int E, const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds,    \
                                    hipStream_t s);                                                                   \
     hipError_t dispatch_pgrad_##tag(int E, const void *f, const void *g, double *grad4, const LctArgs &a, int nb,    \
-                                    int bs, size_t lds, hipStream_t s);
+                                    int bs, size_t lds, hipStream_t s);                                              \
+    hipError_t dispatch_lct_window_##tag(int E, const void *in, void *out, const LctArgs &a, int nb, int bs,         \
+                                         size_t lds, hipStream_t s);
 // Fractional transform beyond one work-group: length L = 2N = L1 L2.
 struct FrLArgs {
     int N, L, L1, L2;

@@ -6,10 +6,32 @@
 namespace lctk {
 
 namespace {
+template <typename R, int E, int NF1, int NF2>
+hipError_t launch_interp_fixed(const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s)
+{
+    using V = typename Vec<R>::T;
+    if (hipError_t r = allow_lds((const void *)k_interp<R, E, NF1, NF2>, lds); r != hipSuccess)
+        return r;
+    hipLaunchKernelGGL((k_interp<R, E, NF1, NF2>), dim3((unsigned)a.batch), dim3(a.T), lds, s, (const V *)in, (V *)ws,
+                       a);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_interp_t(int E, const void *in, void *ws, const InterpArgs &a, size_t lds, hipStream_t s)
 {
     using V = typename Vec<R>::T;
+    // compile-time schedules for the common FP32 (N, P N) pairs
+    if constexpr (sizeof(R) == 4) {
+        const int M = a.N * a.P;
+        if (E == 16 && is_fixed_sched(a.sc1, a.N, 16) && is_fixed_sched(a.sc2, M, 16)) {
+#define Y(n, m)                                                                                                      \
+    if (a.N == n && M == m)                                                                                          \
+        return launch_interp_fixed<R, 16, n, m>(in, ws, a, lds, s);
+            Y(1024, 2048) Y(1024, 4096) Y(2048, 4096) Y(2048, 8192) Y(4096, 8192) Y(4096, 16384) Y(8192, 16384)
+#undef Y
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e: {                                                                                                        \
@@ -43,16 +65,16 @@ hipError_t launch_interp(bool fp64, int E, const void *in, void *ws, const Inter
 
 hipError_t launch_window(bool fp64, const void *fine, void *out, int N, int M, int off, int64_t batch, hipStream_t s)
 {
-    const int64_t total = batch * N;
+    if (batch <= 0)
+        return hipSuccess;
     const int bs = 256;
-    const int64_t want = (total + bs - 1) / bs;
-    const unsigned nb = (unsigned)(want < 65536 ? want : 65536);
+    const dim3 grid((unsigned)((N + bs - 1) / bs), (unsigned)(batch < 65535 ? batch : 65535));
     if (fp64)
-        hipLaunchKernelGGL(k_window<double>, dim3(nb), dim3(bs), 0, s, (const double2 *)fine, (double2 *)out, N, M,
-                           off, total);
+        hipLaunchKernelGGL(k_window<double>, grid, dim3(bs), 0, s, (const double2 *)fine, (double2 *)out, N, M, off,
+                           batch);
     else
-        hipLaunchKernelGGL(k_window<float>, dim3(nb), dim3(bs), 0, s, (const float2 *)fine, (float2 *)out, N, M, off,
-                           total);
+        hipLaunchKernelGGL(k_window<float>, grid, dim3(bs), 0, s, (const float2 *)fine, (float2 *)out, N, M, off,
+                           batch);
     return hipGetLastError();
 }
 

@@ -32,12 +32,35 @@ __device__ __forceinline__ void fft_lds_part(C<R> *v, C<R> *lds, int t, int T, c
     }
 }
 
+// Compile-time-schedule version (E = 16) of fft_lds_part.
+template <int E, int N, int S, int NS, typename R>
+__device__ __forceinline__ void fft_lds_part_fixed(C<R> *v, C<R> *lds, int t, bool active)
+{
+    constexpr int NST = fixed_nstages(N, E);
+    if constexpr (S < NST) {
+        constexpr int RAD = fixed_radix(N, E, S);
+        constexpr int T = N / E;
+        if (active)
+            stage_compute<E, RAD>(v, t, T, NS);
+        if constexpr (S + 1 < NST) {
+            __syncthreads();
+            if (active)
+                stage_write<E, RAD>(lds, v, t, T, NS);
+            __syncthreads();
+            if (active)
+                stage_read<E>(lds, v, t, T);
+        }
+        fft_lds_part_fixed<E, N, S + 1, NS * RAD>(v, lds, t, active);
+    }
+}
+
 // One signal per work-group.  With c_n = (1/N) sum_k f_k e^{-2 pi i n k / N}
 // (n = k for k < N/2, k - N above; for even N the coefficient at n = -N/2 is
 // split in halves between -N/2 and +N/2), the fine samples are
 //   g_m = sum_n c_n e^{-i pi n (P - 1) / (P N)} e^{2 pi i n m / (P N)},
 // i.e. f's trigonometric interpolant at x_0 + (h / P)(m - (P - 1)/2).
-template <typename R, int E>
+// NF1, NF2 > 0: the lengths N and P N with their compile-time schedules (E = 16).
+template <typename R, int E, int NF1 = 0, int NF2 = 0>
 __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__restrict__ in,
                                                  typename Vec<R>::T *__restrict__ out, InterpArgs a)
 {
@@ -56,7 +79,10 @@ __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__res
 #pragma unroll
     for (int e = 0; e < E; ++e)
         v[e] = act ? ldc<R>(src + t + T1 * e) : C<R>{(R)0, (R)0};
-    fft_lds_part<E>(v, lds, t, T1, a.sc1, act);
+    if constexpr (NF1 > 0)
+        fft_lds_part_fixed<E, NF1, 0, 1>(v, lds, t, act);
+    else
+        fft_lds_part<E>(v, lds, t, T1, a.sc1, act);
 
     // 2) the zero-padded, twisted coefficients in natural order (LDS, unpadded)
     __syncthreads(); // the DFT's last exchange has been read
@@ -65,19 +91,16 @@ __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__res
     __syncthreads();
     if (act) {
         const R inv = (R)1 / (R)N;
-        const int64_t twoM = 2 * (int64_t)M;
+        const double inv2M = 0.5 / (double)M;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + T1 * e;
             const int n = k < (N + 1) / 2 ? k : k - N; // -floor(N/2) .. ceil(N/2) - 1
             const C<R> c = cscale(v[e], inv);
-            // twist e^{-i pi n (P-1) / (P N)}: -n (P-1) / (2 P N) turns, reduced exactly
-            auto twisted = [&](int nn) {
-                int64_t num = ((int64_t)nn * (P - 1)) % twoM;
-                if (num < 0)
-                    num += twoM;
-                return cmul(c, cis_turns_from<R>(frac_turns(-(double)num / (double)twoM)));
-            };
+            // twist e^{-i pi n (P-1) / (P N)}: -n (P-1) / (2 M) turns; |n (P-1)| < M
+            // (|n| <= N/2), so the integer product is exact and the turns lie in
+            // (-1/2, 1/2) without a reduction
+            auto twisted = [&](int nn) { return cmul(c, cis_turns_from<R>(-(double)(nn * (P - 1)) * inv2M)); };
             if ((N & 1) == 0 && 2 * n == -N) {
                 // Nyquist coefficient: half at -N/2, half at +N/2
                 const C<R> h0 = cscale(twisted(n), (R)0.5), h1 = cscale(twisted(-n), (R)0.5);
@@ -94,22 +117,27 @@ __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__res
 #pragma unroll
     for (int e = 0; e < E; ++e)
         v[e] = cconj(lds[t + T * e]);
-    fft_lds<E>(v, lds, t, T, a.sc2);
+    if constexpr (NF2 > 0)
+        fft_lds_fixed<E, NF2>(v, lds, t);
+    else
+        fft_lds<E>(v, lds, t, T, a.sc2);
 #pragma unroll
     for (int e = 0; e < E; ++e)
         stc<R>(dst + t + T * e, cconj(v[e]));
 }
 
 // out[s][j] = fine[s][j + off], j < N (the fine transform's rows at y_j).
+// Grid: (ceil(N / blockDim), up to 65535 signal rows, each row striding over
+// the batch); no division per element.
 template <typename R>
 __global__ void k_window(const typename Vec<R>::T *__restrict__ fine, typename Vec<R>::T *__restrict__ out, int N,
-                         int M, int off, int64_t total)
+                         int M, int off, int64_t batch)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = i / N;
-        const int j = (int)(i - s * N);
-        out[i] = fine[s * M + off + j];
-    }
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= N)
+        return;
+    for (int64_t s = blockIdx.y; s < batch; s += gridDim.y)
+        out[s * N + j] = fine[s * M + off + j];
 }
 
 } // namespace lctk
