@@ -55,6 +55,27 @@ def test_oversampled_matches_oracle(dtype, N, P):
         assert rel(y, oracle.lct_oversampled(fin[s], *M[s], P)) <= TOL[dtype], (N, P, s)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("N,P", [(1024, 4), (4096, 2), (4096, 4), (1536, 3)])
+def test_oversampled_batch(dtype, N, P):
+    """Several signals through one plan (the fine transform stores its middle block straight
+    to the output where a windowed instantiation exists: fine lengths 4096, 8192, 16384;
+    the others transform in full and copy the window)."""
+    if P * N > lct.lct_max_single_pass(prec_of(dtype)):
+        pytest.skip("fine grid beyond the single-pass limit")
+    B = 5
+    g = np.random.default_rng(7 * N + P)
+    M = workloads.sl2_params(1, g)[0]
+    gp = workloads.gaussian_params(B, g)
+    x = torch.from_numpy(workloads.chirped_gaussians(oracle.nodes(N), gp)).to("cuda").to(dtype)
+    fin = x.cpu().numpy().astype(np.complex128)
+    print(f"[oversampled batch] N={N} P={P} {dtype} M={M}", flush=True)
+    p = lct.lct_plan_create(N, *M, precision=prec_of(dtype))
+    y = lct.lct_exec_oversampled(p, P, x).cpu().numpy()
+    for s in (0, 2, B - 1):
+        assert rel(y[s], oracle.lct_oversampled(fin[s], *M, P)) <= TOL[dtype], (N, P, s)
+
+
 @pytest.mark.parametrize("N,M,gp,P", [
     (1024, (2.0, 0.1, (2.0 * 0.3 - 1) / 0.1, 0.3), (0.5, 0.5, 0.3), 4),
     (1024, (-1.5, -0.06, (-1.5 * -0.4 - 1) / -0.06, -0.4), (-0.3, 0.6, -0.5), 4),
