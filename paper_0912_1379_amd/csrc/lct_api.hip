@@ -686,13 +686,15 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
     // values per thread: E divides N (and so P N), schedules with radices
     // dividing E exist for both lengths, at most 1024 threads
     InterpArgs a{};
-    // (FP64 tries 8 first: at E = 16 the interpolation kernel spills)
+    // (the fused kernel's width first where it has an instantiation; otherwise
+    // FP64 tries 8 first: at E = 16 the interpolation kernel spills)
     int E = 0;
     static const int widths32[] = {16, 20, 24, 12, 10, 8, 15, 6, 5, 4, 3, 2};
     static const int widths64[] = {8, 16, 12, 10, 20, 24, 6, 15, 5, 4, 3, 2};
     const int *widths = fp64 ? widths64 : widths32;
-    for (int w = 0; w < 12; ++w) {
-        const int cand = widths[w];
+    const int fw = oversampled_fused_width(fp64, (int)N, (int)M);
+    for (int w = fw > 0 ? -1 : 0; w < 12; ++w) {
+        const int cand = w < 0 ? fw : widths[w];
         if (N % cand || M / cand > 1024 || !interp_width_ok(cand))
             continue;
         const Sched s1 = greedy_sched(N, cand, 16, false), s2 = greedy_sched(M, cand, 16, false);
@@ -713,17 +715,24 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
     const size_t lds = (size_t)lds_elems((int)M) * (fp64 ? 16 : 8);
     if (lds > LDS_BYTES)
         return LCT_ERR_UNSUPPORTED;
-    if ((rc = hip_status(launch_interp(fp64, E, in, ws, a, lds, stream))))
-        return rc;
     // the fine grid is the scaled grid s x'_m of M points, s = 1 / sqrt(P):
     // step h / P over the same span; its outputs 4 b x'_m / (pi s) hold the
     // Algorithm's y_j at m = j + (P - 1) N / 2
     const LctConst k = lct_const_scaled(M, p->a, p->b, p->c, p->d, 1.0 / sqrt((double)P));
     if (!lct_const_finite(k))
         return LCT_ERR_ARG;
+    const int off = (int)((P - 1) * N / 2);
+    a.k = k;
+    a.win_off = off;
+    // one kernel for the interpolation, the fine transform and the window where
+    // an instantiation exists (the fine samples stay on chip)
+    const hipError_t fe = launch_oversampled_fused(fp64, E, in, out, a, lds, stream);
+    if (fe != hipErrorNotSupported)
+        return hip_status(fe);
+    if ((rc = hip_status(launch_interp(fp64, E, in, ws, a, lds, stream))))
+        return rc;
     // the fine transform stores only its middle block straight to out where a
     // windowed instantiation exists; otherwise in full, then the window is copied
-    const int off = (int)((P - 1) * N / 2);
     rc = lct_launch_window(M, fp64, &k, ws, out, batch, off, (int)N, stream);
     if (rc != LCT_ERR_UNSUPPORTED)
         return rc;

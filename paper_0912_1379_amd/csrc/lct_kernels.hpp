@@ -145,8 +145,18 @@ struct InterpArgs {
     int T1;         // threads of the length-N DFT: N / E (<= T)
     int64_t batch;
     Sched sc1, sc2; // schedules of the length-N and length-P N DFTs
+    LctConst k;     // fused launch: the fine-grid transform's constants
+    int win_off;    //   and the first of its N stored outputs
 };
 bool interp_width_ok(int E);
+// The interpolation, the fine-grid transform and the window in one kernel
+// (compile-time schedules for the common (N, P N) pairs at E = 16: FP32 up to
+// P N = 16384, FP64 up to 8192); hipErrorNotSupported elsewhere.
+// oversampled_fused_width: the E of the fused instantiation for (N, M = P N),
+// 0 if there is none.
+int oversampled_fused_width(bool fp64, int N, int M);
+hipError_t launch_oversampled_fused(bool fp64, int E, const void *in, void *out, const InterpArgs &a, size_t lds,
+                                    hipStream_t s);
 
 // LCT of a complex matrix at the Algorithm's complex output nodes: per-n^2
 // log-modulus and turns (double-double) of the pre- and post-diagonals, and

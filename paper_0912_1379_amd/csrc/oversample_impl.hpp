@@ -126,6 +126,88 @@ __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__res
         stc<R>(dst + t + T * e, cconj(v[e]));
 }
 
+// The interpolation (as k_interp), the LCT of the P N fine samples (pre-chirp,
+// DFT, post-chirp with the constants a.k) and the window [a.win_off,
+// a.win_off + N) in one work-group per signal: the fine samples never leave
+// LDS and registers.  Compile-time schedules for N and M = P N at E values
+// per thread (T = M / E <= LB threads).  FP64 takes LB = 512 (256 VGPRs per
+// thread): at 1024 threads the 128-register cap spills.
+template <typename R, int E, int NF1, int NF2, int LB = 1024>
+__global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__restrict__ in,
+                                                   typename Vec<R>::T *__restrict__ out, InterpArgs a)
+{
+    using V = typename Vec<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<R> *lds = reinterpret_cast<C<R> *>(smem_raw);
+    constexpr int N = NF1, M = NF2, T = M / E, T1 = N / E;
+    const int P = a.P;
+    const int t = (int)threadIdx.x;
+    const int64_t s = blockIdx.x;
+    const bool act = t < T1;
+    const V *src = in + (size_t)s * N;
+
+    // 1) c = DFT_N(f) / N on the first T1 threads
+    C<R> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = act ? ldc<R>(src + t + T1 * e) : C<R>{(R)0, (R)0};
+    fft_lds_part_fixed<E, N, 0, 1>(v, lds, t, act);
+
+    // 2) the zero-padded, twisted coefficients in natural order (LDS, unpadded)
+    __syncthreads();
+    for (int i = t; i < M; i += T)
+        lds[i] = C<R>{(R)0, (R)0};
+    __syncthreads();
+    if (act) {
+        const R inv = (R)1 / (R)N;
+        const double inv2M = 0.5 / (double)M;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + T1 * e;
+            const int n = k < (N + 1) / 2 ? k : k - N;
+            const C<R> c = cscale(v[e], inv);
+            auto twisted = [&](int nn) { return cmul(c, cis_turns_from<R>(-(double)(nn * (P - 1)) * inv2M)); };
+            if (2 * n == -N) {
+                const C<R> h0 = cscale(twisted(n), (R)0.5), h1 = cscale(twisted(-n), (R)0.5);
+                lds[M + n] = h0;
+                lds[-n] = h1;
+            } else {
+                lds[n < 0 ? M + n : n] = twisted(n);
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3) the fine samples g = conj(DFT_M(conj(d))), kept in registers
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        v[e] = cconj(lds[t + T * e]);
+    fft_lds_fixed<E, M>(v, lds, t);
+
+    // 4) the fine-grid LCT: pre-chirp, DFT, post-chirp; the window stored
+    const LctConst &k = a.k;
+    const double inv2M = 0.5 / (double)M;
+    {
+        ChirpSeq<R> cin(thread_chirp(k.pre_hi, k.pre_lo, true, t, T, M, inv2M));
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = cmul(cconj(v[e]), cin.next());
+    }
+    fft_lds_fixed<E, M>(v, lds, t);
+    {
+        const R mag = (R)k.amp_mag;
+        ChirpSeq<R> cout(thread_chirp(k.post_hi, k.post_lo, true, t, T, M, inv2M, k.amp_turns));
+        V *dst = out + (size_t)s * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<R> y = cscale(cmul(v[e], cout.next()), mag);
+            const unsigned q = (unsigned)(t + T * e - a.win_off);
+            if (q < (unsigned)N)
+                stc<R>(dst + q, y);
+        }
+    }
+}
+
 // out[s][j] = fine[s][j + off], j < N (the fine transform's rows at y_j).
 // Grid: (ceil(N / blockDim), up to 65535 signal rows, each row striding over
 // the batch); no division per element.

@@ -56,11 +56,14 @@ def test_oversampled_matches_oracle(dtype, N, P):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
-@pytest.mark.parametrize("N,P", [(1024, 4), (4096, 2), (4096, 4), (1536, 3)])
+@pytest.mark.parametrize("N,P", [(1024, 2), (1024, 4), (2048, 2), (2048, 4), (4096, 2), (4096, 4), (8192, 2),
+                                 (512, 8), (1536, 3)])
 def test_oversampled_batch(dtype, N, P):
-    """Several signals through one plan (the fine transform stores its middle block straight
-    to the output where a windowed instantiation exists: fine lengths 4096, 8192, 16384;
-    the others transform in full and copy the window)."""
+    """Several signals through one plan, on each of the three paths: one fused kernel for
+    the (N, P N) pairs with compile-time schedules (the first seven); the interpolation,
+    then the fine transform storing its middle block straight to the output (N = 512,
+    P = 8: fine length 4096); the interpolation, the full fine transform and the window
+    copy (N = 1536, P = 3)."""
     if P * N > lct.lct_max_single_pass(prec_of(dtype)):
         pytest.skip("fine grid beyond the single-pass limit")
     B = 5
