@@ -723,7 +723,6 @@ int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t b
         return LCT_ERR_ARG;
     const int off = (int)((P - 1) * N / 2);
     a.k = k;
-    a.win_off = off;
     // one kernel for the interpolation, the fine transform and the window where
     // an instantiation exists (the fine samples stay on chip)
     const hipError_t fe = launch_oversampled_fused(fp64, E, in, out, a, lds, stream);

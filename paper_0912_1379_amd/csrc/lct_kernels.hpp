@@ -146,7 +146,6 @@ struct InterpArgs {
     int64_t batch;
     Sched sc1, sc2; // schedules of the length-N and length-P N DFTs
     LctConst k;     // fused launch: the fine-grid transform's constants
-    int win_off;    //   and the first of its N stored outputs
 };
 bool interp_width_ok(int E);
 // The interpolation, the fine-grid transform and the window in one kernel

@@ -127,11 +127,18 @@ __global__ __launch_bounds__(1024) void k_interp(const typename Vec<R>::T *__res
 }
 
 // The interpolation (as k_interp), the LCT of the P N fine samples (pre-chirp,
-// DFT, post-chirp with the constants a.k) and the window [a.win_off,
-// a.win_off + N) in one work-group per signal: the fine samples never leave
+// DFT, post-chirp with the constants a.k) and the window [(P - 1) N / 2,
+// (P + 1) N / 2) in one work-group per signal: the fine samples never leave
 // LDS and registers.  Compile-time schedules for N and M = P N at E values
 // per thread (T = M / E <= LB threads).  FP64 takes LB = 512 (256 VGPRs per
 // thread): at 1024 threads the 128-register cap spills.
+// With 2P dividing E, N / 2 is a whole number of thread strides T, so the
+// zero-padded spectrum's support [0, N/2] and [M - N/2, M) is, in the layout
+// t + T e, the values e < EL and e >= E - EL (EL = E / 2P) of every thread and
+// e = EL of thread 0 (position N/2, the upper half of the Nyquist
+// coefficient): the other values are zeros known at compile time, and the
+// zero fill of LDS is not needed.  Likewise the window is the values
+// e in [E0, E0 + N / T) (E0 = (P - 1) N / 2T) of every thread.
 template <typename R, int E, int NF1, int NF2, int LB = 1024>
 __global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__restrict__ in,
                                                    typename Vec<R>::T *__restrict__ out, InterpArgs a)
@@ -139,8 +146,11 @@ __global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__res
     using V = typename Vec<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<R> *lds = reinterpret_cast<C<R> *>(smem_raw);
-    constexpr int N = NF1, M = NF2, T = M / E, T1 = N / E;
-    const int P = a.P;
+    constexpr int N = NF1, M = NF2, T = M / E, T1 = N / E, P = M / N;
+    static_assert(M % N == 0 && P >= 2 && N % 2 == 0 && E % (2 * P) == 0, "spectrum support in whole strides");
+    constexpr int EL = E / (2 * P);
+    constexpr int OFF = (P - 1) * N / 2, E0 = OFF / T, NW = N / T;
+    static_assert(OFF % T == 0 && N % T == 0 && E0 + NW <= E, "window in whole strides");
     const int t = (int)threadIdx.x;
     const int64_t s = blockIdx.x;
     const bool act = t < T1;
@@ -153,18 +163,16 @@ __global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__res
         v[e] = act ? ldc<R>(src + t + T1 * e) : C<R>{(R)0, (R)0};
     fft_lds_part_fixed<E, N, 0, 1>(v, lds, t, act);
 
-    // 2) the zero-padded, twisted coefficients in natural order (LDS, unpadded)
-    __syncthreads();
-    for (int i = t; i < M; i += T)
-        lds[i] = C<R>{(R)0, (R)0};
-    __syncthreads();
+    // 2) the twisted coefficients at their positions of the length-M spectrum
+    //    (natural order, unpadded; only the support is written)
+    __syncthreads(); // the DFT's last exchange has been read
     if (act) {
         const R inv = (R)1 / (R)N;
         const double inv2M = 0.5 / (double)M;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + T1 * e;
-            const int n = k < (N + 1) / 2 ? k : k - N;
+            const int n = k < N / 2 ? k : k - N; // -N/2 .. N/2 - 1
             const C<R> c = cscale(v[e], inv);
             auto twisted = [&](int nn) { return cmul(c, cis_turns_from<R>(-(double)(nn * (P - 1)) * inv2M)); };
             if (2 * n == -N) {
@@ -180,8 +188,14 @@ __global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__res
 
     // 3) the fine samples g = conj(DFT_M(conj(d))), kept in registers
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        v[e] = cconj(lds[t + T * e]);
+    for (int e = 0; e < E; ++e) {
+        if (e < EL || e >= E - EL)
+            v[e] = cconj(lds[t + T * e]);
+        else if (e == EL)
+            v[e] = t == 0 ? cconj(lds[T * EL]) : C<R>{(R)0, (R)0};
+        else
+            v[e] = C<R>{(R)0, (R)0};
+    }
     fft_lds_fixed<E, M>(v, lds, t);
 
     // 4) the fine-grid LCT: pre-chirp, DFT, post-chirp; the window stored
@@ -196,15 +210,11 @@ __global__ __launch_bounds__(LB) void k_os_fused(const typename Vec<R>::T *__res
     fft_lds_fixed<E, M>(v, lds, t);
     {
         const R mag = (R)k.amp_mag;
-        ChirpSeq<R> cout(thread_chirp(k.post_hi, k.post_lo, true, t, T, M, inv2M, k.amp_turns));
+        ChirpSeq<R> cout(seq_chirp(k.post_hi, k.post_lo, true, t + OFF, T, M, inv2M, k.amp_turns));
         V *dst = out + (size_t)s * N;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const C<R> y = cscale(cmul(v[e], cout.next()), mag);
-            const unsigned q = (unsigned)(t + T * e - a.win_off);
-            if (q < (unsigned)N)
-                stc<R>(dst + q, y);
-        }
+        for (int e = 0; e < NW; ++e)
+            stc<R>(dst + t + T * e, cscale(cmul(v[E0 + e], cout.next()), mag));
     }
 }
 
