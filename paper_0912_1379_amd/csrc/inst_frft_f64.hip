@@ -21,8 +21,7 @@ hipError_t dispatch_frft_f64(int E, const void *in, void *out, const FrArgs &a, 
             break;
         }
     }
-    // E = 8, the FP64 default (16 values of a row and of the kernel per thread
-    // would not fit the registers of a 512-thread work-group)
+    // E = 8 (the tuner's alternative to the default 16)
     if (E == 8 && is_fixed_sched(a.sc, 2 * a.N, 8)) {
         switch (2 * a.N) {
 #define X(n)                                                                                                         \

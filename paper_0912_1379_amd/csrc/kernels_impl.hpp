@@ -462,14 +462,16 @@ __device__ __forceinline__ void fft_any(C<R> *v, C<R> *lds, int t, int T, const 
 // schedule.  SREAD: the instantiation for a spectrum shared by the batch
 // (SPEC_READ), which reads it from the workspace at the product instead of
 // holding it in registers through the data's FFT; with those registers free
-// it is asked for four waves per SIMD (two 512-thread work-groups per CU at
-// L = 8192, against one for the kernel that transforms its own spectrum).
+// it is asked for four waves per SIMD (FP32: two 512-thread work-groups per CU
+// at L = 8192, against one for the kernel that transforms its own spectrum),
+// FP64 below 1024 threads for two (its LDS holds it to one work-group per CU
+// at L = 8192; four waves would cut it to 128 registers and spill).
 // DB (fixed lengths): the FFT exchanges alternate between two LDS buffers
 // (twice the LDS, one barrier per stage); used where the registers already
 // hold the work-group to one per CU.
 template <typename R, int E, int LFIX = 0, int LB = max_block(sizeof(R) == 8, E), bool SREAD = false,
           bool DB = false>
-__global__ __launch_bounds__(LB, SREAD ? 4 : 1) void k_frft(
+__global__ __launch_bounds__(LB, SREAD ? (sizeof(R) == 8 && LB < 1024 ? 2 : 4) : 1) void k_frft(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ out, FrArgs args)
 {
     using V = typename Vec<R>::T;
@@ -624,7 +626,7 @@ inline hipError_t launch_frft_t(const void *in, void *out, const FrArgs &a, int 
                                 hipStream_t s)
 {
     auto kern = k_frft<R, E, LFIX, LB>;
-    if constexpr (LFIX > 0 && sizeof(R) == 8 && E == 8) {
+    if constexpr (LFIX > 0 && sizeof(R) == 8 && (E == 8 || E == 16)) {
         if (a.spec_mode == SPEC_READ)
             kern = k_frft<R, E, LFIX, LB, true>;
     }

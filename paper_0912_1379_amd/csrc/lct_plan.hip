@@ -101,7 +101,7 @@ int choose_E(int64_t N, bool fp64, bool frft)
     static const int l1[] = {1, 0};
     static const int l23_64[] = {12, 6, 24, 18, 0};
     static const int l25_64[] = {10, 20, 0};
-    static const int l2_fr64[] = {8, 16, 4, 2, 0};
+    static const int l2_fr64[] = {8, 16, 4, 2, 0}; // FP64 two-pass convolution rows
     const int *lst;
     if (p2 && p3 && p5) lst = l235;
     else if (p2 && p3) lst = fp64 ? l23_64 : l23;
@@ -197,7 +197,12 @@ Tiling tiling_of(int64_t Nfft, bool fp64, int E, int S, const Sched &sc, size_t 
 
 Tiling default_tiling(int64_t Nfft, bool fp64, bool frft, size_t extra)
 {
-    const int E = choose_E(Nfft, fp64, frft);
+    // The single-pass convolution takes the LCT's widths: in FP64, 16 values
+    // per thread on half the threads fit the registers where 8 on 1024
+    // threads spilled.  (The two-pass convolution's rows keep FP64 at 8
+    // first: choose_E with frft set.)
+    (void)frft;
+    const int E = choose_E(Nfft, fp64, false);
     if (E == 0)
         return Tiling{};
     const int T = (int)(Nfft / E);
