@@ -492,7 +492,8 @@ def bench_next(args):
     convolution per signal with the kernel's spectrum computed once), the LCT at the Algorithm's
     complex output nodes (lct_complex_exec) for the bilateral Laplace matrix (0, i, 0), and the
     aliasing-aware LCT (lct_exec_oversampled: interpolation onto the P times finer grid, the
-    transform there, the middle block; P = 4 in FP32, 2 in FP64).  The step is the complex-node LCT; each leg
+    transform there, the middle block; P = 4 in FP32, 2 in FP64), and the LCT of samples on the scaled
+    input grid s x_k (lct_plan_create_scaled, s = 1/2).  The step is the complex-node LCT; each leg
     reports its time, rate, the relative L2 error of 2 signals against the oracle and the oracle's
     time on them."""
     import torch
@@ -509,8 +510,8 @@ def bench_next(args):
     legs = {}
     cpu = {"seconds": 0.0, "samples": 0}
 
-    def leg(name, dt, run, ref_fn, nref=2):
-        x = torch.from_numpy(f).to("cuda").to(dt)
+    def leg(name, dt, run, ref_fn, nref=2, data=None):
+        x = torch.from_numpy(f if data is None else data).to("cuda").to(dt)
         y = torch.empty_like(x)
         steps = args.steps if dt == torch.complex64 else max(3, args.steps // 2)
         ms, ms_kernel, wall = time_launches(lambda: run(x, y), steps, args.warmup)
@@ -558,16 +559,29 @@ def bench_next(args):
         leg(name, dt, lambda x, y: lct.lct_exec_oversampled(plan, p, x, out=y, ws=ws),
             lambda fin: oracle.lct_oversampled(fin, *M, p))
         legs[name]["P"] = p
+    # scaled input grid: samples on s x_k, outputs at 4 b x_j / (pi s)
+    sc = 0.5
+    Ms = (0.6, 0.8, (0.6 * 1.1 - 1.0) / 0.8, 1.1)
+    fs = workloads.chirped_gaussians(sc * xn, gp)
+    for name, dt in (("scaled_f32", torch.complex64), ("scaled_f64", torch.complex128)):
+        if dt == torch.complex128 and args.no_fp64:
+            continue
+        prec = lct.LCT_FP64 if dt == torch.complex128 else lct.LCT_FP32
+        plan = lct.lct_plan_create_scaled(N, *Ms, sc, precision=prec)
+        leg(name, dt, lambda x, y: lct.lct_exec(plan, x, out=y), lambda fin: oracle.lct(fin, *Ms, scale=sc),
+            data=fs)
+        legs[name]["s"] = sc
     head = legs["complex_nodes_f32"]
     out = {
         "metric": "complex samples/s, LCT of a complex matrix at the Algorithm's complex output nodes",
         "value": head["value"], "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"complex-matrix, same-grid and oversampled LCTs, {B} signals x N={N}",
+        "config": {"workload": f"complex-matrix, same-grid, oversampled and scaled-grid LCTs, {B} signals x N={N}",
                    "signals": B, "N": N, "complex_matrix": "(0, i, 0): bilateral Laplace",
                    "same_grid_matrix": [str(a), str(b), str(d)],
-                   "oversampled": {"M": list(M), "P": {"f32": 4, "f64": 2}}},
+                   "oversampled": {"M": list(M), "P": {"f32": 4, "f64": 2}},
+                   "scaled": {"M": list(Ms), "s": sc}},
         "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": head["achieved_GBps"] / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_lct_cx (FP32)",
                      "kernel_ms": head["kernel_ms"], "algorithmic_bytes_per_launch": 16.0 * samples},
