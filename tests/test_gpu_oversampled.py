@@ -79,6 +79,22 @@ def test_oversampled_batch(dtype, N, P):
         assert rel(y[s], oracle.lct_oversampled(fin[s], *M, P)) <= TOL[dtype], (N, P, s)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_oversampled_fused_in_place(dtype):
+    """in == out through the one-kernel path (N = 1024, P = 4): every work-group reads its
+    signal before it writes any output."""
+    N, P, B = 1024, 4, 3
+    g = np.random.default_rng(21)
+    M = workloads.sl2_params(1, g)[0]
+    x = torch.from_numpy(workloads.chirped_gaussians(oracle.nodes(N), workloads.gaussian_params(B, g))).to(
+        "cuda").to(dtype)
+    p = lct.lct_plan_create(N, *M, precision=prec_of(dtype))
+    ref = lct.lct_exec_oversampled(p, P, x).cpu().numpy()
+    y = x.clone()
+    lct.lct_exec_oversampled(p, P, y, out=y)
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("N,M,gp,P", [
     (1024, (2.0, 0.1, (2.0 * 0.3 - 1) / 0.1, 0.3), (0.5, 0.5, 0.3), 4),
     (1024, (-1.5, -0.06, (-1.5 * -0.4 - 1) / -0.06, -0.4), (-0.3, 0.6, -0.5), 4),
