@@ -62,12 +62,28 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct_cx(const typename Vec<R>
     const int64_t sig = (int64_t)blockIdx.x * a.S + sl;
     const bool live = sig < a.batch;
     const double inv2N = 0.5 / (double)N;
-    const typename Vec<R>::T *src = in + (size_t)(live ? sig : 0) * N;
-    typename Vec<R>::T *dst = out + (size_t)(live ? sig : 0) * N;
+    using V = typename Vec<R>::T;
+    [[maybe_unused]] const V *src = in + (size_t)(live ? sig : 0) * N;
+    [[maybe_unused]] V *dst = out + (size_t)(live ? sig : 0) * N;
+    // FP32: one buffer descriptor per work-group over its live signals, the
+    // element offsets constant (slots past the batch read zeros); FP64 keeps
+    // plain loads and stores (its 128-bit buffer stores timed slower here)
+    const int64_t first = (int64_t)blockIdx.x * a.S;
+    const int64_t nlive = a.batch - first < a.S ? a.batch - first : a.S;
+    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rin =
+        make_rsrc(in + first * N, (uint32_t)(nlive * N * (int64_t)sizeof(V)));
+    [[maybe_unused]] const __amdgpu_buffer_rsrc_t rout =
+        make_rsrc(out + first * N, (uint32_t)(nlive * N * (int64_t)sizeof(V)));
+    [[maybe_unused]] const int voff = (sl * N + t) * (int)sizeof(V);
+    [[maybe_unused]] const int sstep = T * (int)sizeof(V);
     C<R> v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        v[e] = live ? ldc<R>(src + t + T * e) : C<R>{(R)0, (R)0};
+    for (int e = 0; e < E; ++e) {
+        if constexpr (sizeof(R) == 4)
+            v[e] = Buf<R>::load(rin, voff, e * sstep);
+        else
+            v[e] = live ? ldc<R>(src + t + T * e) : C<R>{(R)0, (R)0};
+    }
     {
         CxDiag<R> pre(a.k.pre_mag, a.k.pre_hi, a.k.pre_lo, t, T, N, inv2N);
 #pragma unroll
@@ -84,8 +100,13 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct_cx(const typename Vec<R>
         CxDiag<R> post(a.k.post_mag, a.k.post_hi, a.k.post_lo, t, T, N, inv2N);
         const C<R> amp{(R)a.k.amp_re, (R)a.k.amp_im};
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            stc<R>(dst + t + T * e, cmul(cmul(v[e], post.at(e)), amp));
+        for (int e = 0; e < E; ++e) {
+            const C<R> y = cmul(cmul(v[e], post.at(e)), amp);
+            if constexpr (sizeof(R) == 4)
+                Buf<R>::store(y, rout, voff, e * sstep);
+            else
+                stc<R>(dst + t + T * e, y);
+        }
     }
 }
 
