@@ -253,6 +253,15 @@ def bench_ragged(args):
     z = workloads.frft_orders(count, g)
     gp = workloads.gaussian_params(count, g)
     params = np.where(kinds[:, None] == lct.LCT_KIND_LCT, M, np.stack([z.real, z.imag, 0 * z.real, 0 * z.real], 1))
+    if args.ragged_subset != "all":
+        # one part of the same batch (per-kind timings and counters): the long signals are those
+        # beyond one work-group's registers (LCT N > 6144, fractional 2N > 6144)
+        is_lct = kinds == lct.LCT_KIND_LCT
+        big = np.where(is_lct, N > 6144, 2 * N > 6144)
+        sel = {"lct": is_lct, "frft": ~is_lct, "lct_big": is_lct & big, "frft_big": ~is_lct & big,
+               "small": ~big}[args.ragged_subset]
+        N, kinds, params, gp = N[sel], kinds[sel], params[sel], gp[sel]
+        count = int(sel.sum())
     desc = lct.make_descriptors(N, kinds, params)
     parts = []
     for i, n in enumerate(N):
@@ -272,7 +281,7 @@ def bench_ragged(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"ragged: {count} signals, N in [256, 65536] (2^k, 3 2^k, 5 2^k), half LCT half "
                                "fractional transform, one persistent launch", "signals": count, "samples": samples,
-                   "items": plan.items, "grid": plan.grid},
+                   "items": plan.items, "grid": plan.grid, "subset": args.ragged_subset},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": gbps / PEAK_HBM_GBPS, "traffic": None, "kernel": "k_ragged", "kernel_ms": ms_kernel,
                      "algorithmic_bytes_per_launch": 16.0 * samples},
@@ -763,6 +772,8 @@ def main():
                     help="frft workload: skip the shared-order (precomputed kernel spectrum) leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the built-in geometry heuristic instead of autotuning first")
+    ap.add_argument("--ragged-subset", default="all", choices=["all", "lct", "frft", "lct_big", "frft_big", "small"],
+                    help="ragged workload: time one part of the batch only")
     ap.add_argument("--workload", choices=["batched", "ragged", "large", "fit", "frft", "xft", "next"],
                     default="batched",
                     help="batched: 4096 x N=4096 (default); ragged: 10,000 uneven signals in one launch; "
