@@ -26,8 +26,13 @@ __device__ __forceinline__ FrConst fr_const_of(const FrLArgs &a, int64_t s)
 
 // Pass 1 over columns n2 of the length-L sequence (element i = n1 L2 + n2).
 // blockIdx.x < batch * tiles handles the data (FR_DATA), the rest the
-// kernel sequence (FR_KERN).
-template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+// kernel sequence (FR_KERN).  NF > 0: the column length L1 = NF with its
+// compile-time radix schedule.
+// With E even, L1 = T1 E is even and i < N = L1 L2 / 2 exactly when
+// n1 < L1 / 2, i.e. e < E / 2: the data's upper half is the zero padding, and
+// the kernel is at m = i for e < E / 2 and at m = L - i from there on (both
+// give m = N at i = N), so each value is formed once.
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E), int NF = 0>
 __global__ __launch_bounds__(LB) void k_frl1(
     const typename Vec<R>::T *__restrict__ in, typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
@@ -61,12 +66,27 @@ __global__ __launch_bounds__(LB) void k_frl1(
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = i0 + Di * e;
-            const C<R> w = dch.next();
             C<R> x = {(R)0, (R)0};
-            if (i < N && !k.special)
-                x = cmul(ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i)), w);
+            if constexpr (E % 2 == 0) {
+                if (e < E / 2) {
+                    const C<R> w = dch.next();
+                    if (!k.special)
+                        x = cmul(ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i)), w);
+                }
+            } else {
+                const C<R> w = dch.next();
+                if (i < N && !k.special)
+                    x = cmul(ldc<R>(in + (size_t)s * N + (k.hankel ? N - 1 - i : i)), w);
+            }
             v[e] = x;
         }
+    } else if constexpr (E % 2 == 0) {
+        // kernel at m = i (e < E/2), m = L - i = (L - i0 - Di E/2) - Di (e - E/2) after
+        GaussSeq<R> lo(k.kmag, k.kph_hi, k.kph_lo, i0, Di);
+        GaussSeq<R> hi(k.kmag, k.kph_hi, k.kph_lo, L - i0 - Di * (E / 2), -Di);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            v[e] = e < E / 2 ? lo.next() : hi.next();
     } else {
         // kernel at m = i for i <= N, m = L - i = (L - i0) - Di e beyond
         GaussSeq<R> lo(k.kmag, k.kph_hi, k.kph_lo, i0, Di), hi(k.kmag, k.kph_hi, k.kph_lo, L - i0, -Di);
@@ -78,7 +98,7 @@ __global__ __launch_bounds__(LB) void k_frl1(
     }
 
     C<R> *lds = smem + (size_t)sl * lds_elems(L1);
-    fft_lds<E>(v, lds, t, T1, a.sc1);
+    fft_any<R, E, NF>(v, lds, t, T1, a.sc1);
 
     {
         const double A = -(double)umod24(n2 * t, L) / (double)L;
@@ -108,7 +128,8 @@ __global__ __launch_bounds__(LB) void k_frl1(
 //   sum_k P_k W_L^(-n k) = sum_k1 W_L1^(-n1 k1) [W_L^(-n2 k1) sum_k2 W_L2^(-n2 k2) P_(k1 + L1 k2)],
 // and the conjugate of the bracket (the forward length-L2 DFT of conj(P),
 // times W_L^(+n2 k1), W_L = e^(-2 pi i / L)) is stored into R0 at n2 L1 + k1.
-template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+// NF > 0: the row length L2 = NF with its compile-time radix schedule.
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E), int NF = 0>
 __global__ __launch_bounds__(LB) void k_frl2(typename Vec<R>::T *__restrict__ ws, FrLArgs a)
 {
     using V = typename Vec<R>::T;
@@ -137,18 +158,18 @@ __global__ __launch_bounds__(LB) void k_frl2(typename Vec<R>::T *__restrict__ ws
     }
     C<R> *lds = smem + (size_t)r * lds_elems(a.L2);
     if (a.spec_mode != SPEC_READ)
-        fft_lds<E>(w, lds, t, T2, a.sc2);
+        fft_any<R, E, NF>(w, lds, t, T2, a.sc2);
     if (write_spec) {
 #pragma unroll
         for (int e = 0; e < E; ++e)
             stc<R>(R1 + (size_t)(t + T2 * e) * L1 + k1, w[e]);
         return;
     }
-    fft_lds<E>(v, lds, t, T2, a.sc2);
+    fft_any<R, E, NF>(v, lds, t, T2, a.sc2);
 #pragma unroll
     for (int e = 0; e < E; ++e)
         v[e] = cconj(cmul(v[e], w[e]));
-    fft_lds<E>(v, lds, t, T2, a.sc2);
+    fft_any<R, E, NF>(v, lds, t, T2, a.sc2);
     const double A = -(double)umod24(k1 * t, L) / (double)L;
     const double B = -(double)umod24(k1 * T2, L) / (double)L;
 #pragma unroll
@@ -160,8 +181,10 @@ __global__ __launch_bounds__(LB) void k_frl2(typename Vec<R>::T *__restrict__ ws
 // R0[n2 L1 + k1] gives the conjugate of the inverse transform at
 // j = n2 + L2 n1; transposed through LDS (consecutive threads, consecutive j)
 // it is conjugated, multiplied by the diagonal and the constant, and the
-// first N outputs are stored.
-template <typename R, int E, int LB = max_block(sizeof(R) == 8, E)>
+// first N outputs are stored.  NF > 0: the column length L1 = NF with its
+// compile-time radix schedule.  With E even the kept outputs j < N are the
+// positions n1 < L1 / 2, i.e. e < E / 2.
+template <typename R, int E, int LB = max_block(sizeof(R) == 8, E), int NF = 0>
 __global__ __launch_bounds__(LB) void k_frl3(const typename Vec<R>::T *__restrict__ ws,
                                                                        typename Vec<R>::T *__restrict__ out, FrLArgs a)
 {
@@ -186,10 +209,11 @@ __global__ __launch_bounds__(LB) void k_frl3(const typename Vec<R>::T *__restric
     for (int e = 0; e < E; ++e)
         v[e] = ldc<R>(R0 + (size_t)(n20 + sl) * L1 + t + T1 * e);
     C<R> *lds = smem + (size_t)sl * lds_elems(L1);
-    fft_lds<E>(v, lds, t, T1, a.sc1);
+    fft_any<R, E, NF>(v, lds, t, T1, a.sc1);
+    constexpr int EK = E % 2 == 0 ? E / 2 : E; // values that can hold a kept output
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e)
+    for (int e = 0; e < EK; ++e)
         lds[lds_pad(t + T1 * e)] = v[e];
     __syncthreads();
     const int sl2 = tid % Cc;
@@ -199,7 +223,7 @@ __global__ __launch_bounds__(LB) void k_frl3(const typename Vec<R>::T *__restric
     const int j0 = n20 + sl2 + L2 * t2;
     GaussSeq<R> och(k.omag, k.oph_hi, k.oph_lo, 2 * j0 - N + 1, 2 * L2 * T1);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < EK; ++e) {
         const int n1 = t2 + T1 * e;
         const int j = j0 + L2 * T1 * e;
         const C<R> w = och.next();
@@ -230,17 +254,33 @@ __global__ void k_fr_special(const typename Vec<R>::T *__restrict__ in, typename
 // The default widths (E = 16 FP32, 8 FP64) also have an instantiation bounded
 // at 256 threads, used whenever the work-group fits it: with the 1024-thread
 // bound the pass-2 kernel, which holds a data row and a kernel row per thread,
-// is held to 128 registers and spills.
+// is held to 128 registers and spills.  Those also have compile-time radix
+// schedules for the sub-lengths 256 .. 4096.
 template <typename R, int E> constexpr bool has_tight_frl() { return E == (sizeof(R) == 8 ? 8 : 16); }
+#define LCT_FRL_FIXED_LIST(X) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename R, int E>
 inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl1<R, E>;
-    if constexpr (has_tight_frl<R, E>())
-        if (bs <= 256)
+    if constexpr (has_tight_frl<R, E>()) {
+        if (bs <= 256) {
             kern = k_frl1<R, E, 256>;
+            if (is_fixed_sched(a.sc1, a.L1, E)) {
+                switch (a.L1) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        kern = k_frl1<R, E, 256, n>;                                                                                 \
+        break;
+                    LCT_FRL_FIXED_LIST(X)
+#undef X
+                default:
+                    break;
+                }
+            }
+        }
+    }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)in, (V *)ws, a);
@@ -252,9 +292,23 @@ inline hipError_t launch_frl2_t(void *ws, const FrLArgs &a, int nb, int bs, size
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl2<R, E>;
-    if constexpr (has_tight_frl<R, E>())
-        if (bs <= 256)
+    if constexpr (has_tight_frl<R, E>()) {
+        if (bs <= 256) {
             kern = k_frl2<R, E, 256>;
+            if (is_fixed_sched(a.sc2, a.L2, E)) {
+                switch (a.L2) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        kern = k_frl2<R, E, 256, n>;                                                                                 \
+        break;
+                    LCT_FRL_FIXED_LIST(X)
+#undef X
+                default:
+                    break;
+                }
+            }
+        }
+    }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (V *)ws, a);
@@ -267,9 +321,23 @@ inline hipError_t launch_frl3_t(const void *ws, void *out, const FrLArgs &a, int
 {
     using V = typename Vec<R>::T;
     auto kern = k_frl3<R, E>;
-    if constexpr (has_tight_frl<R, E>())
-        if (bs <= 256)
+    if constexpr (has_tight_frl<R, E>()) {
+        if (bs <= 256) {
             kern = k_frl3<R, E, 256>;
+            if (is_fixed_sched(a.sc1, a.L1, E)) {
+                switch (a.L1) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        kern = k_frl3<R, E, 256, n>;                                                                                 \
+        break;
+                    LCT_FRL_FIXED_LIST(X)
+#undef X
+                default:
+                    break;
+                }
+            }
+        }
+    }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, st, (const V *)ws, (V *)out, a);
