@@ -251,13 +251,13 @@ __global__ void k_fr_special(const typename Vec<R>::T *__restrict__ in, typename
     }
 }
 
-// The default widths (E = 16 FP32, 8 FP64) also have an instantiation bounded
+// The default widths (E = 16; FP64 also 8) also have an instantiation bounded
 // at 256 threads, used whenever the work-group fits it: with the 1024-thread
 // bound the pass-2 kernel, which holds a data row and a kernel row per thread,
 // is held to 128 registers and spills.  Those also have compile-time radix
-// schedules for the sub-lengths 256 .. 4096.
-template <typename R, int E> constexpr bool has_tight_frl() { return E == (sizeof(R) == 8 ? 8 : 16); }
-#define LCT_FRL_FIXED_LIST(X) X(256) X(512) X(1024) X(2048) X(4096)
+// schedules for the sub-lengths 64 .. 4096.
+template <typename R, int E> constexpr bool has_tight_frl() { return E == 16 || (sizeof(R) == 8 && E == 8); }
+#define LCT_FRL_FIXED_LIST(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename R, int E>
 inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
