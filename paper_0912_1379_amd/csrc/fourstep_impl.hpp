@@ -189,8 +189,9 @@ __global__ __launch_bounds__(LB, (MF && LB == 256) ? 3 : 1) void k_fs2(typename 
 }
 
 // Sub-lengths with compile-time schedules (E = 16): the four-step splits of
-// 2^16 .. 2^24.
-#define LCT_FS_FIXED_LIST(X) X(256) X(512) X(1024) X(2048) X(4096)
+// the powers of two from the first two-pass length (2^14 FP64, 2^15 FP32) to
+// 2^24.
+#define LCT_FS_FIXED_LIST(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)
