@@ -31,6 +31,8 @@ template <> struct CxDiag<float> {
     {
     }
     __device__ __forceinline__ C<float> at(int e) { return gauss_at(g, e); }
+    // the phase alone (a diagonal of zero log-modulus rate)
+    __device__ __forceinline__ C<float> phase(int e) { return chirp_at<float>(g.ph, e); }
 };
 template <> struct CxDiag<double> {
     // values in order e = 0, 1, ... (at(e) once per e): the phase walked by
@@ -43,6 +45,7 @@ template <> struct CxDiag<double> {
     {
     }
     __device__ __forceinline__ C<double> at(int e) { return cscale(c.next(), exp(fmax(gauss_logmod(g, e), -1000.0))); }
+    __device__ __forceinline__ C<double> phase(int) { return c.next(); }
 };
 
 // NFIX > 0: the length's compile-time radix schedule (E = 16); with
@@ -84,11 +87,20 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct_cx(const typename Vec<R>
         else
             v[e] = live ? ldc<R>(src + t + T * e) : C<R>{(R)0, (R)0};
     }
+    // A diagonal whose log-modulus rate is zero (Im(a/b) = 0 for the pre-,
+    // Im(bd) = 0 for the post-diagonal) is a pure phase: the exponential is
+    // skipped (a branch uniform over the launch).
     {
         CxDiag<R> pre(a.k.pre_mag, a.k.pre_hi, a.k.pre_lo, t, T, N, inv2N);
+        if (a.k.pre_mag == 0.0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            v[e] = cmul(v[e], pre.at(e));
+            for (int e = 0; e < E; ++e)
+                v[e] = cmul(v[e], pre.phase(e));
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                v[e] = cmul(v[e], pre.at(e));
+        }
     }
     if constexpr (NFIX > 0 && HX)
         fft_lds_fixed_half<E, NFIX>(v, reinterpret_cast<R *>(smem_raw) + (size_t)sl * lds_elems(N), t);
@@ -99,13 +111,20 @@ __global__ __launch_bounds__(LB, HX ? 3 : 1) void k_lct_cx(const typename Vec<R>
     if (live) {
         CxDiag<R> post(a.k.post_mag, a.k.post_hi, a.k.post_lo, t, T, N, inv2N);
         const C<R> amp{(R)a.k.amp_re, (R)a.k.amp_im};
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const C<R> y = cmul(cmul(v[e], post.at(e)), amp);
+        auto store = [&](int e, C<R> y) {
             if constexpr (sizeof(R) == 4)
                 Buf<R>::store(y, rout, voff, e * sstep);
             else
                 stc<R>(dst + t + T * e, y);
+        };
+        if (a.k.post_mag == 0.0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                store(e, cmul(cmul(v[e], post.phase(e)), amp));
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                store(e, cmul(cmul(v[e], post.at(e)), amp));
         }
     }
 }
