@@ -22,6 +22,8 @@ MATRICES = [
     (-0.4 + 0.5j, 1.2 - 0.1j, 0.2 + 0.05j),
     (1.5, -0.8 - 0.1j, -0.4 - 0.2j),               # real a, b in the lower half-plane
     (0.5, 1.0, -0.5),                              # real matrix
+    (0.0, 0.6 - 0.2j, 1.1 + 0.5j),                 # pre-diagonal a pure phase, post damped
+    (0.9 + 0.1j, 0.6 - 0.2j, 0.0),                 # pre damped, post-diagonal a pure phase
 ]
 
 
