@@ -292,7 +292,9 @@ int lct_complex_nodes(int64_t N, double b_re, double b_im, double *y);
  * and with every prime factor of P dividing N (the two DFTs of the
  * interpolation share one thread layout); else LCT_ERR_UNSUPPORTED.  ws: DEVICE, 16-byte
  * aligned, lct_oversampled_workspace_size(N, P, prec, batch) bytes (the P N
- * fine samples per signal; LCT_ERR_WORKSPACE if smaller).  in == out allowed.
+ * fine samples per signal; LCT_ERR_WORKSPACE if smaller; required even where
+ * the common (N, P N) pairs run in one kernel whose fine samples stay on chip
+ * and leave it untouched).  in == out allowed.
  */
 size_t lct_oversampled_workspace_size(int64_t N, int P, lct_precision prec, int64_t batch);
 int lct_exec_oversampled(lct_plan p, int P, const void *in, void *out, int64_t batch, void *ws, size_t ws_bytes,
