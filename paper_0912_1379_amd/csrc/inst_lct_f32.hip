@@ -21,6 +21,20 @@ hipError_t dispatch_lct_f32(int E, const void *in, void *out, const LctArgs &a, 
             break;
         }
     }
+    // lengths 3 2^k (E = 24) and 5 2^k (E = 20) with their compile-time schedules
+    if ((E == 24 || E == 20) && is_fixed_sched(a.sc, a.N, E) && (a.N / E < 256 || a.S == 1)) {
+        switch (a.N) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_lct_t<float, e, n>(in, out, a, nb, bs, lds, s);                                            \
+        break;
+            X(24, 1536) X(24, 3072) X(24, 6144) X(24, 12288) X(20, 2560) X(20, 5120) X(20, 10240)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

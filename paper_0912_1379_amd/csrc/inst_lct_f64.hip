@@ -27,6 +27,20 @@ hipError_t dispatch_lct_f64(int E, const void *in, void *out, const LctArgs &a, 
             break;
         }
     }
+    // lengths 3 2^k (E = 12) and 5 2^k (E = 10) with their compile-time schedules
+    if ((E == 12 || E == 10) && is_fixed_sched(a.sc, a.N, E) && (a.N / E < 256 || a.S == 1)) {
+        switch (a.N) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_lct_t<double, e, n>(in, out, a, nb, bs, lds, s);                                           \
+        break;
+            X(12, 1536) X(12, 3072) X(12, 6144) X(10, 2560) X(10, 5120)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

@@ -42,9 +42,9 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda").to(dtype)
 
 
-SIZES32 = [1, 2, 3, 4, 5, 8, 12, 16, 30, 64, 96, 100, 128, 250, 256, 384, 1000, 1024, 1536, 2048, 3000,
-           4096, 5120, 6144, 8192, 10240, 12288, 15360, 16384]
-SIZES64 = [1, 2, 3, 8, 30, 128, 1000, 1024, 3000, 4096, 6144, 8192]
+SIZES32 = [1, 2, 3, 4, 5, 8, 12, 16, 30, 64, 96, 100, 128, 250, 256, 384, 1000, 1024, 1536, 2048, 2560, 3000,
+           3072, 4096, 5120, 6144, 8192, 10240, 12288, 15360, 16384]
+SIZES64 = [1, 2, 3, 8, 30, 128, 1000, 1024, 1536, 2560, 3000, 3072, 4096, 5120, 6144, 8192]
 
 
 def check_many(N, dtype, batch=3, seed=0, rows=None):
