@@ -4,6 +4,18 @@
 
 namespace lctk {
 
+namespace {
+template <int L>
+hipError_t launch_frft24(const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds, hipStream_t s)
+{
+    auto kern = k_frft<float, 24, L>;
+    if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, (const float2 *)in, (float2 *)out, a);
+    return hipGetLastError();
+}
+} // namespace
+
 hipError_t dispatch_frft_f32(int E, const void *in, void *out, const FrArgs &a, int nb, int bs, size_t lds,
                              hipStream_t s)
 {
@@ -16,6 +28,21 @@ hipError_t dispatch_frft_f32(int E, const void *in, void *out, const FrArgs &a, 
             return launch_frft_t<float, 16, n, tight_bound(n)>(in, out, a, nb, bs, lds, s);                          \
         return launch_frft_t<float, 16, n>(in, out, a, nb, bs, lds, s);
             X(512) X(1024) X(2048) X(4096) X(8192) X(16384)
+#undef X
+        default:
+            break;
+        }
+    }
+    // convolution lengths 3 2^k at E = 24, every spectrum mode through the
+    // instantiation that holds the kernel's spectrum in registers (the one that
+    // reads a shared spectrum at the product spills at E = 24; at E = 20, for
+    // 5 2^k, every compile-time form spills where the runtime one does not)
+    if (E == 24 && is_fixed_sched(a.sc, 2 * a.N, 24)) {
+        switch (2 * a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_frft24<n>(in, out, a, nb, bs, lds, s);
+            X(3072) X(6144) X(12288)
 #undef X
         default:
             break;

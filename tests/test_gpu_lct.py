@@ -278,7 +278,7 @@ ZS = [0.5, 0.6 * np.exp(-1.1j), -0.7 + 0.2j, 0.9 * np.exp(2.5j), 1j, -1j, np.exp
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex64, 2e-5), (torch.complex128, 1e-12)])
-@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 100, 1000, 4096])
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 64, 100, 1000, 1536, 3072, 4096, 6144])
 def test_frft(dtype, tol, N):
     x_n = oracle.nodes(N)
     gen = np.random.default_rng(N)
