@@ -33,6 +33,19 @@ hipError_t dispatch_frft_f64(int E, const void *in, void *out, const FrArgs &a, 
             break;
         }
     }
+    // convolution lengths 3 2^k at E = 12 (the kernel's spectrum held in
+    // registers in every spectrum mode, 234-248 VGPRs, no spills)
+    if (E == 12 && is_fixed_sched(a.sc, 2 * a.N, 12)) {
+        switch (2 * a.N) {
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return launch_frft_t<double, 12, n>(in, out, a, nb, bs, lds, s);
+            X(3072) X(6144)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \
