@@ -41,6 +41,32 @@ hipError_t launch_cx_t(int E, const void *in, void *out, const CxArgs &a, int nb
             break;
         }
     }
+    // lengths 3 2^k and 5 2^k at the widths the planner gives them (FP32 24 / 20,
+    // FP64 12 / 10)
+    constexpr int E3 = sizeof(R) == 8 ? 12 : 24, E5 = sizeof(R) == 8 ? 10 : 20;
+    if ((E == E3 || E == E5) && is_fixed_sched(a.sc, a.N, E) && (a.N / E < 256 || a.S == 1)) {
+        switch (a.N) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_one<R, e, n>(in, out, a, nb, bs, lds, s);                                                  \
+        break;
+            X(E3, 1536) X(E3, 3072) X(E3, 6144) X(E5, 2560) X(E5, 5120)
+#undef X
+        case 12288:
+            if constexpr (sizeof(R) == 4)
+                if (E == E3)
+                    return launch_one<R, E3, 12288>(in, out, a, nb, bs, lds, s);
+            break;
+        case 10240:
+            if constexpr (sizeof(R) == 4)
+                if (E == E5)
+                    return launch_one<R, E5, 10240>(in, out, a, nb, bs, lds, s);
+            break;
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

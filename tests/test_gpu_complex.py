@@ -53,7 +53,7 @@ def gaussian_logmag(gp, a, b, d, y):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
-@pytest.mark.parametrize("N", [1, 2, 3, 64, 1000, 4096, 6144])
+@pytest.mark.parametrize("N", [1, 2, 3, 64, 1000, 3072, 4096, 5120, 6144])
 @pytest.mark.parametrize("M", MATRICES)
 def test_complex_nodes_match_oracle(dtype, N, M):
     a, b, d = M
