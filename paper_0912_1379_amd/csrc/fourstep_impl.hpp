@@ -192,6 +192,12 @@ __global__ __launch_bounds__(LB, (MF && LB == 256) ? 3 : 1) void k_fs2(typename 
 // the powers of two from the first two-pass length (2^14 FP64, 2^15 FP32) to
 // 2^24.
 #define LCT_FS_FIXED_LIST(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+// Sub-lengths 3 2^k and 5 2^k of the four-step splits of such lengths, at the
+// widths the planner gives them (FP32 24 / 20, FP64 12 / 10).
+#define LCT_FS_FIXED3_F32(X) X(24, 192) X(24, 384) X(24, 768) X(24, 1536) X(24, 3072)
+#define LCT_FS_FIXED5_F32(X) X(20, 160) X(20, 320) X(20, 640) X(20, 1280) X(20, 2560)
+#define LCT_FS_FIXED3_F64(X) X(12, 96) X(12, 192) X(12, 384) X(12, 768) X(12, 1536)
+#define LCT_FS_FIXED5_F64(X) X(10, 80) X(10, 160) X(10, 320) X(10, 640) X(10, 1280)
 
 template <typename R, int E, bool MF = false, int NFIX = 0, int LB = max_block(sizeof(R) == 8, E)>
 inline hipError_t launch_fs1_t(const void *in, void *out, const FsArgs &a, int nb, int bs, size_t lds, hipStream_t s)

@@ -16,6 +16,19 @@ hipError_t dispatch_fs1_f64(int E, const void *in, void *out, const FsArgs &a, i
             break;
         }
     }
+    if ((E == 12 || E == 10) && is_fixed_sched(a.sc1, a.N1, E)) {
+        switch (a.N1) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_fs1_t<double, e, false, n>(in, out, a, nb, bs, lds, s);                                                  \
+        break;
+            LCT_FS_FIXED3_F64(X) LCT_FS_FIXED5_F64(X)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

@@ -16,6 +16,19 @@ hipError_t dispatch_fs2_f32(int E, void *out, const FsArgs &a, int nb, int bs, s
             break;
         }
     }
+    if ((E == 24 || E == 20) && is_fixed_sched(a.sc2, a.N2, E)) {
+        switch (a.N2) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_fs2_t<float, e, false, n>(out, a, nb, bs, lds, s);                                                  \
+        break;
+            LCT_FS_FIXED3_F32(X) LCT_FS_FIXED5_F32(X)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

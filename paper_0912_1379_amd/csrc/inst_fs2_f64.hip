@@ -16,6 +16,19 @@ hipError_t dispatch_fs2_f64(int E, void *out, const FsArgs &a, int nb, int bs, s
             break;
         }
     }
+    if ((E == 12 || E == 10) && is_fixed_sched(a.sc2, a.N2, E)) {
+        switch (a.N2) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_fs2_t<double, e, false, n>(out, a, nb, bs, lds, s);                                                  \
+        break;
+            LCT_FS_FIXED3_F64(X) LCT_FS_FIXED5_F64(X)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \
