@@ -259,6 +259,37 @@ __global__ void k_fr_special(const typename Vec<R>::T *__restrict__ in, typename
 template <typename R, int E> constexpr bool has_tight_frl() { return E == 16 || (sizeof(R) == 8 && E == 8); }
 #define LCT_FRL_FIXED_LIST(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
+// Column factors 3 2^k and 5 2^k of passes 1 and 3 at the widths the planner
+// gives them (FP32 24 / 20, FP64 12 / 10), with compile-time schedules.
+#define LCT_FRL_FIX3_24(X) X(192) X(384) X(768) X(1536) X(3072)
+#define LCT_FRL_FIX5_20(X) X(160) X(320) X(640) X(1280) X(2560)
+#define LCT_FRL_FIX3_12(X) X(96) X(192) X(384) X(768) X(1536)
+#define LCT_FRL_FIX5_10(X) X(80) X(160) X(320) X(640) X(1280)
+// (passes 1 and 3 take the same arguments: a source, a destination, FrLArgs)
+template <typename R>
+using FrlColsKernel = void (*)(const typename Vec<R>::T *, typename Vec<R>::T *, FrLArgs);
+template <typename R, int E>
+inline FrlColsKernel<R> frl_cols_fixed(int L1, const Sched &sc, bool pass3)
+{
+    constexpr int LB = max_block(sizeof(R) == 8, E);
+    if (!is_fixed_sched(sc, L1, E))
+        return nullptr;
+#define X(n)                                                                                                         \
+    case n:                                                                                                          \
+        return pass3 ? k_frl3<R, E, LB, n> : k_frl1<R, E, LB, n>;
+    if constexpr (sizeof(R) == 4 && E == 24) {
+        switch (L1) { LCT_FRL_FIX3_24(X) default: break; }
+    } else if constexpr (sizeof(R) == 4 && E == 20) {
+        switch (L1) { LCT_FRL_FIX5_20(X) default: break; }
+    } else if constexpr (sizeof(R) == 8 && E == 12) {
+        switch (L1) { LCT_FRL_FIX3_12(X) default: break; }
+    } else if constexpr (sizeof(R) == 8 && E == 10) {
+        switch (L1) { LCT_FRL_FIX5_10(X) default: break; }
+    }
+#undef X
+    return nullptr;
+}
+
 template <typename R, int E>
 inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int nb, int bs, size_t lds, hipStream_t st)
 {
@@ -280,6 +311,10 @@ inline hipError_t launch_frl1_t(const void *in, void *ws, const FrLArgs &a, int 
                 }
             }
         }
+    }
+    if constexpr (!has_tight_frl<R, E>()) {
+        if (FrlColsKernel<R> f = frl_cols_fixed<R, E>(a.L1, a.sc1, false))
+            kern = f;
     }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
@@ -337,6 +372,10 @@ inline hipError_t launch_frl3_t(const void *ws, void *out, const FrLArgs &a, int
                 }
             }
         }
+    }
+    if constexpr (!has_tight_frl<R, E>()) {
+        if (FrlColsKernel<R> f = frl_cols_fixed<R, E>(a.L1, a.sc1, true))
+            kern = f;
     }
     if (hipError_t e = allow_lds((const void *)kern, lds); e != hipSuccess)
         return e;
