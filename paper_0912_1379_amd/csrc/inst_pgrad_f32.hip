@@ -21,6 +21,22 @@ hipError_t dispatch_pgrad_f32(int E, const void *f, const void *g, double *grad4
             break;
         }
     }
+    // lengths 3 2^k and 5 2^k at the planner's widths, work-groups of up to 256
+    // threads (their compile-time schedules fit that bound's registers with few
+    // or no spills; the runtime-schedule kernel spills 300 VGPRs and more)
+    if ((E == 24 || E == 20) && bs <= 256 && is_fixed_sched(a.sc, a.N, E)) {
+        switch (a.N) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_pgrad_t<float, e, n, 256>(f, g, grad4, a, nb, bs, lds, s);                                  \
+        break;
+            X(24, 1536) X(24, 3072) X(24, 6144) X(20, 2560) X(20, 5120)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

@@ -21,6 +21,22 @@ hipError_t dispatch_pgrad_f64(int E, const void *f, const void *g, double *grad4
             break;
         }
     }
+    // lengths 3 2^k and 5 2^k at the planner's widths, work-groups of up to 256
+    // threads (their compile-time schedules fit that bound's registers with few
+    // or no spills; the runtime-schedule kernel spills 300 VGPRs and more)
+    if ((E == 12 || E == 10) && bs <= 256 && is_fixed_sched(a.sc, a.N, E)) {
+        switch (a.N) {
+#define X(e, n)                                                                                                      \
+    case n:                                                                                                          \
+        if (E == e)                                                                                                  \
+            return launch_pgrad_t<double, e, n, 256>(f, g, grad4, a, nb, bs, lds, s);                                  \
+        break;
+            X(12, 1536) X(12, 3072) X(10, 2560)
+#undef X
+        default:
+            break;
+        }
+    }
     switch (E) {
 #define X(e)                                                                                                         \
     case e:                                                                                                          \

@@ -194,7 +194,7 @@ def test_adjoint(dtype, N):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex64, 2e-4), (torch.complex128, 1e-10)])
-@pytest.mark.parametrize("N", [64, 256, 2048])
+@pytest.mark.parametrize("N", [64, 256, 2048, 2560, 3072])
 def test_param_grad(dtype, tol, N):
     M, f = c1_inputs(N, 3, 13)
     gen = np.random.default_rng(N)
